@@ -1,0 +1,195 @@
+/*
+ * cls.h -- C ABI of the MI355X Chord Length Sampling library (libcls_hip.so).
+ *
+ * The library runs Algorithm A of Chord Length Sampling (CLS) -- Section 4 of
+ * Larmier, Lam, Brantley, Malvagi, Palmer, Zoia, "Monte Carlo Chord Length
+ * Sampling for d-dimensional Markov binary mixtures" (arXiv 1708.00765) -- for
+ * single-speed, isotropically scattering particles in a binary Markov mixture,
+ * on hand-written HIP kernels for gfx950 (AMD Instinct MI355X).
+ *
+ * Problem (Section 2): a box of side L with leakage on the two faces normal to
+ * x and mirror reflection on the lateral faces; materials i = 0, 1 with total
+ * cross section Sigma_i, scattering ratio c_i = Sigma_s,i / Sigma_i and mean
+ * chord length Lambda_i; volume fractions p_i = Lambda_i / (Lambda_0 + Lambda_1).
+ * Observables (Section 2): transmission T = current out of x = L, reflection
+ * R = current out of x = 0, absorption A, and the scalar flux integrated over
+ * the lateral coordinates and directions on a uniform x-mesh, all per source
+ * history, each with a one-sigma statistical error.
+ *
+ * Conventions for every function below:
+ *   - Every entry point returns cls_status (CLS_OK = 0); no C++ exception
+ *     crosses the ABI. On failure nothing is modified and cls_last_error()
+ *     returns a thread-local message naming the cause.
+ *   - Host pointers are owned by the caller and only read or written during
+ *     the call. Device pointers passed in stay owned by the caller and must
+ *     outlive every run that uses them.
+ *   - A problem handle is not thread-safe; distinct handles are independent.
+ *   - Results are a function of (problem parameters, histories, seed) only:
+ *     history h of a run uses the random stream keyed by (seed, h), whatever
+ *     the batch, slot or launch shape. Integer tallies are bitwise
+ *     reproducible; FP64 sums are reproducible up to the order of atomic
+ *     additions (about 1e-15 relative).
+ */
+#ifndef CLS_H
+#define CLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CLS_OK = 0,
+    CLS_ERR_INVALID_ARG = 1,   /* a parameter is out of its documented range   */
+    CLS_ERR_OUT_OF_MEMORY = 2, /* host or device allocation failed              */
+    CLS_ERR_DEVICE = 3,        /* a HIP runtime call failed                     */
+    CLS_ERR_NOT_READY = 4,     /* asynchronous work is still running            */
+    CLS_ERR_EVENT_CAP = 5,     /* a history hit the per-history flight cap      */
+    CLS_ERR_STATE = 6,         /* call out of order (e.g. read before any run)  */
+    CLS_ERR_NO_DEVICE = 7      /* no usable gfx950 device                       */
+} cls_status;
+
+/* Source (Section 2): suite I = normalized incident angular flux on x = 0
+ * (rod: entering along +x; slab/2D/3D: cosine-weighted inward direction,
+ * Sec. 4.1-4.3); suite II = uniform isotropic interior source. */
+enum { CLS_SRC_FACE_X0 = 0, CLS_SRC_VOLUME = 1 };
+
+/* Boundary bits, one per face in the order x-, x+, y-, y+, z-, z+; a set bit
+ * means mirror reflection, a clear bit leakage. The paper's box (Section 2)
+ * leaks on x- and x+ and reflects on every lateral face that exists: y for
+ * d = 2, y and z for d = 3. CLS_BC_DEFAULT selects exactly that; any other
+ * value is accepted only if it equals it. */
+enum { CLS_BC_DEFAULT = 0xFFFFFFFFu };
+#define CLS_BC_FACE(i) (1u << (i))
+
+/* Flags. */
+enum {
+    CLS_F_D1_SLAB = 1u << 0,        /* d = 1 is the paper's slab (continuous x-cosine,
+                                       Sec. 4.1); without it d = 1 is the rod (+-x)   */
+    CLS_F_COLLISION_FLUX = 1u << 1, /* collision estimator for the flux mesh; default
+                                       is the track-length estimator (Sec. 3.3)       */
+    CLS_F_FP32 = 1u << 2,           /* FP32 flight arithmetic, FP64 x-position and
+                                       tallies; default is FP64 throughout            */
+    CLS_F_TRACE = 1u << 3           /* FP64 only: record an event hash and the flight
+                                       count of the first histories (cls_read_trace)  */
+};
+
+/* Largest flux mesh. */
+#define CLS_MAX_BINS 2048
+
+typedef struct cls_problem cls_problem;
+
+/* Create a problem (host only; no device work, so it is usable without a GPU).
+ *   d          1 (rod, or slab with CLS_F_D1_SLAB), 2 (extruded: square of side L
+ *              in x-y, infinite along z, directions in 3D, Sec. 4.2) or 3 (cube).
+ *   L          box side, finite and > 0.
+ *   sigma_t[2] total cross sections, finite and > 0.
+ *   c[2]       scattering ratios in [0, 1].
+ *   lambda[2]  mean chord lengths, finite and > 0.
+ *   source     CLS_SRC_FACE_X0 or CLS_SRC_VOLUME.
+ *   boundaries CLS_BC_DEFAULT or the equal explicit mask (see above).
+ *   nbins      flux mesh size in [1, CLS_MAX_BINS]; bin k = [k L/K, (k+1) L/K),
+ *              x = L belongs to the last bin.
+ *   flags      CLS_F_* bits; CLS_F_TRACE requires FP64 (not CLS_F_FP32).
+ *   out        receives the handle (library-owned; free with cls_destroy_problem).
+ * Errors: CLS_ERR_INVALID_ARG for any value outside these ranges or a NaN/Inf;
+ * CLS_ERR_OUT_OF_MEMORY. */
+cls_status cls_create_problem(int d, double L, const double sigma_t[2], const double c[2],
+                              const double lambda[2], int source, uint32_t boundaries,
+                              int nbins, uint32_t flags, cls_problem **out);
+
+/* Release a problem and the device memory the library allocated for it.
+ * Waits for its pending work. NULL is a no-op. */
+void cls_destroy_problem(cls_problem *p);
+
+/* Launch subsequent runs of p on the given hipStream_t (NULL = the default
+ * stream). The stream is borrowed, not owned. */
+cls_status cls_set_stream(cls_problem *p, void *hip_stream);
+
+/* Device bytes one run of p needs (tallies, results and its share of the work
+ * queue); independent of the number of histories except for the trace buffer,
+ * which grows with min(histories, trace_histories). */
+cls_status cls_footprint(const cls_problem *p, uint64_t histories, size_t *bytes);
+
+/* Use caller-owned device memory (e.g. a torch tensor) of at least
+ * cls_footprint() bytes, 256-byte aligned, instead of library allocations.
+ * Pass NULL to return to library-owned memory. */
+cls_status cls_bind_device_memory(cls_problem *p, void *dev_ptr, size_t bytes);
+
+/* Number of leading histories whose trace cls_read_trace returns (CLS_F_TRACE
+ * problems only; default 0). */
+cls_status cls_set_trace_histories(cls_problem *p, uint64_t n);
+
+/* Run `histories` (>= 1) histories with stream key `seed`, replacing the previous
+ * tallies. cls_run blocks until the results are on the host side of the
+ * library; cls_run_async enqueues reset, tracking, finalize and the result copy
+ * on the problem's stream and returns at once (poll with cls_query).
+ * Errors: CLS_ERR_INVALID_ARG (histories == 0), CLS_ERR_NO_DEVICE,
+ * CLS_ERR_DEVICE, CLS_ERR_OUT_OF_MEMORY, CLS_ERR_EVENT_CAP (reported by
+ * cls_run / cls_read_tallies when a history was cut at the flight cap). */
+cls_status cls_run(cls_problem *p, uint64_t histories, uint64_t seed);
+cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed);
+
+/* CLS_OK when the last run of p has completed, CLS_ERR_NOT_READY otherwise. */
+cls_status cls_query(const cls_problem *p);
+
+/* Block until the last run of p has completed. */
+cls_status cls_synchronize(cls_problem *p);
+
+typedef struct {
+    uint64_t histories, transmitted, reflected, absorbed, capped;
+    uint64_t flights, collisions, scatters, interface_crossings, lateral_reflections;
+    uint64_t batches;            /* history chunks used for the batch-means flux error */
+    double T, R, A;              /* per source history                                 */
+    double sigma_T, sigma_R, sigma_A;
+    double total_flux;           /* sum_k flux_k * dx: mean flux score per history     */
+    double sigma_total_flux;     /* from per-history sums                              */
+    double track_ms;             /* duration of the tracking kernel (HIP events)       */
+} cls_tallies;
+
+/* Copy the results of the last completed run. flux and flux_sigma (nbins doubles
+ * each, may be NULL) receive the bin-averaged scalar flux per history and its
+ * batch-means one-sigma error; nbins must equal the problem's mesh size.
+ * Errors: CLS_ERR_STATE (no completed run), CLS_ERR_NOT_READY, CLS_ERR_INVALID_ARG,
+ * CLS_ERR_EVENT_CAP (results are still written). */
+cls_status cls_read_tallies(const cls_problem *p, cls_tallies *out, double *flux,
+                            double *flux_sigma, int nbins);
+
+/* Copy the trace of histories 0 .. n-1 of the last run of a CLS_F_TRACE problem:
+ * hash[i] = FNV-1a-64 over the 4-byte tuples (event code, material, bin low
+ * byte, bin high byte) of history i, flights[i] = its number of flights.
+ * n must not exceed min(histories, trace_histories). */
+cls_status cls_read_trace(const cls_problem *p, uint64_t *hash, uint32_t *flights, uint64_t n);
+
+/* Run n problems in one persistent-kernel launch. All problems must share d,
+ * the slab flag, source, estimator and precision (CLS_ERR_INVALID_ARG
+ * otherwise); histories[i] and seeds[i] belong to problems[i]. Every problem
+ * receives the same tallies it would get from cls_run with the same histories
+ * and seed. The launch uses the stream of problems[0] and is synchronous. */
+cls_status cls_run_batch(cls_problem *const *problems, const uint64_t *histories,
+                         const uint64_t *seeds, int n);
+
+/* Launch shape used by every run of the calling process (0 keeps the
+ * automatic choice): waves per workgroup, workgroups per compute unit, and the
+ * largest number of histories per work chunk. */
+typedef struct {
+    int waves_per_block;
+    int blocks_per_cu;
+    int max_chunk;
+} cls_launch_config;
+cls_status cls_set_launch_config(const cls_launch_config *cfg);
+cls_status cls_get_launch_config(cls_launch_config *cfg);
+
+/* Status name and the calling thread's last error detail. */
+const char *cls_status_string(cls_status s);
+const char *cls_last_error(void);
+
+/* Library version string. */
+const char *cls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,89 @@
+// Internal types shared by the host runtime and the HIP kernels of the CLS
+// library. Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cls {
+
+enum Geom : int { GEOM_ROD = 0, GEOM_SLAB = 1, GEOM_EXT2D = 2, GEOM_CUBE3D = 3 };
+enum Est : int { EST_COLLISION = 0, EST_TRACK = 1 };
+enum Src : int { SRC_FACE = 0, SRC_VOLUME = 1 };
+
+// Trace event codes (same numbering as the documented trace format).
+enum Event : int {
+    EV_SOURCE = 0, EV_INTERFACE = 1, EV_SCATTER = 2, EV_ABSORB = 3,
+    EV_LEAK_XLO = 4, EV_LEAK_XHI = 5,
+    EV_REFL_YLO = 6, EV_REFL_YHI = 7, EV_REFL_ZLO = 8, EV_REFL_ZHI = 9,
+    EV_CAP = 10, EV_NONE = 15
+};
+
+// Integer tallies of one problem (u64 slots in device memory).
+enum Counter : int {
+    C_HISTORIES = 0, C_TRANSMITTED, C_REFLECTED, C_ABSORBED, C_CAPPED,
+    C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_INTERFACES, C_LATERAL, C_BATCHES,
+    C_COUNT = 16
+};
+
+// Result record written by the finalize kernel, in 8-byte words: the
+// C_COUNT integer tallies, then R_HEADER doubles, then flux[K] and
+// flux_sigma[K] (per source history).
+enum Result : int {
+    R_T = 0, R_R, R_A, R_SIGMA_T, R_SIGMA_R, R_SIGMA_A, R_TOTAL, R_SIGMA_TOTAL,
+    R_HEADER = 8
+};
+
+inline size_t record_words(int nbins) { return (size_t)C_COUNT + R_HEADER + 2 * (size_t)nbins; }
+
+// Per-problem parameters and output pointers, one record per problem of a
+// launch (device memory).
+struct alignas(16) DevProblem {
+    double L, inv_dx, dx;
+    double sigma[2], c[2], lam[2];
+    double p0;                  // Lambda_0 / (Lambda_0 + Lambda_1)
+    uint64_t seed;
+    uint64_t histories;
+    uint64_t chunk;             // histories per work item (batch)
+    uint64_t trace_n;           // histories with a recorded trace
+    uint64_t max_steps;         // flight cap per history
+    int32_t nbins;
+    int32_t pad0;
+    uint64_t *counters;         // C_COUNT u64
+    double *sums;               // [0] score sum, [1] score square sum, [2..2+K) S_k, [2+K..2+2K) Q_k
+    uint64_t *record;           // finalize output, record_words(K) words
+    uint64_t *trace_hash;
+    uint32_t *trace_len;
+};
+
+// Everything one tracking launch needs.
+struct TrackArgs {
+    const DevProblem *probs;
+    const uint64_t *item_start;  // nprobs + 1 prefix sums of work items
+    uint64_t *queue_head;        // work-item counter (zeroed before the launch)
+    int nprobs;
+    int lds_stride;              // doubles per tally buffer (>= max nbins + 1, even)
+};
+
+struct LaunchShape {
+    int waves_per_block;
+    int blocks_per_cu;
+    int max_chunk;
+};
+
+// Kernel variants: geometry x estimator x source x precision x trace.
+struct Variant {
+    int geom, est, src;
+    bool fp32, trace;
+};
+
+// Host launchers implemented next to the kernels. They enqueue on `stream`
+// and return the HIP status of the launch.
+hipError_t launch_reset(const DevProblem *d_probs, int nprobs, uint64_t *queue_head,
+                        hipStream_t stream);
+hipError_t launch_track(const Variant &v, const TrackArgs &args, int grid, int block,
+                        size_t lds_bytes, hipStream_t stream);
+hipError_t launch_finalize(const DevProblem *d_probs, int nprobs, hipStream_t stream);
+
+}  // namespace cls
