@@ -102,7 +102,8 @@ def main() -> int:
     scatters = sum(t.scatters for t in tallies)
     lateral = sum(t.lateral_reflections for t in tallies)
     kernel_ms = track_ms / args.steps
-    slots = perf_model.algorithmic_slots(geom, total_hist, flights, scatters, lateral)
+    slots = perf_model.algorithmic_slots(geom, total_hist, flights, scatters, lateral, fp32=True,
+                                         track=not specs[0].collision)
     achieved = slots / (kernel_ms * 1e-3) / 1e12
     peak = perf_model.PEAK_SLOTS_PER_S / 1e12
     log(f"  {ms_per_step:.1f} ms/step, kernel {kernel_ms:.1f} ms, {value:.4g} hist/s, "
@@ -146,12 +147,17 @@ def main() -> int:
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         from oracle import oracle
         from helpers import run_oracle
-        per = 2000
-        t0 = time.perf_counter()
-        for s in specs:
-            run_oracle(s, histories=per, seed=s.seed + 7)
-        cal = time.perf_counter() - t0
-        n_each = max(per, int(per * args.cpu_seconds / max(cal, 1e-3)))
+        # calibrate on a sample large enough that thread start-up does not dominate
+        per = 20000
+        while True:
+            t0 = time.perf_counter()
+            for s in specs:
+                run_oracle(s, histories=per, seed=s.seed + 7)
+            cal = time.perf_counter() - t0
+            if cal > 0.05 * args.cpu_seconds or per >= 10**8:
+                break
+            per *= 4
+        n_each = max(per, int(per * args.cpu_seconds / max(cal, 1e-6)))
         t0 = time.perf_counter()
         for s in specs:
             run_oracle(s, histories=n_each, seed=s.seed + 11)

@@ -19,7 +19,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/cls.h"
+#include "cls.h"
 #include "cls_internal.hpp"
 
 using namespace cls;
@@ -62,8 +62,8 @@ std::mutex g_mu;
 std::vector<DeviceInfo> g_devices;
 LaunchShape g_shape = {0, 0, 0};
 
-constexpr int kDefaultWavesPerBlock = 4;
-constexpr int kDefaultBlocksPerCu = 2;
+constexpr int kDefaultWavesPerBlock = 0;   // 0: chosen per kernel (most resident waves)
+constexpr int kDefaultBlocksPerCu = 0;     // 0: as many as fit (occupancy query)
 constexpr int kDefaultMaxChunk = 16384;
 constexpr uint64_t kDefaultMaxSteps = 100000000ull;
 constexpr size_t kLdsLimit = 65536;
@@ -94,8 +94,8 @@ LaunchShape current_shape()
 {
     std::lock_guard<std::mutex> lk(g_mu);
     LaunchShape s = g_shape;
-    if (s.waves_per_block <= 0) s.waves_per_block = kDefaultWavesPerBlock;
-    if (s.blocks_per_cu <= 0) s.blocks_per_cu = kDefaultBlocksPerCu;
+    if (s.waves_per_block <= 0) s.waves_per_block = kDefaultWavesPerBlock;   // may stay 0
+    if (s.blocks_per_cu <= 0) s.blocks_per_cu = kDefaultBlocksPerCu;   // may stay 0
     if (s.max_chunk <= 0) s.max_chunk = kDefaultMaxChunk;
     return s;
 }
@@ -236,6 +236,14 @@ static void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t 
         out->lam[i] = p->lam[i];
     }
     out->p0 = p->lam[0] / (p->lam[0] + p->lam[1]);
+    out->Lf = (float)p->L;
+    out->p0f = (float)out->p0;
+    for (int i = 0; i < 2; ++i) {
+        out->isig[i] = 1.0 / p->sigma[i];
+        out->isigf[i] = (float)out->isig[i];
+        out->cf[i] = (float)p->c[i];
+        out->lamf[i] = (float)p->lam[i];
+    }
     out->seed = seed;
     out->histories = histories;
     out->chunk = chunk;
@@ -260,22 +268,48 @@ static Variant variant_of(const cls_problem *p)
     return v;
 }
 
-static cls_status shape_for(int max_bins, const DeviceInfo &di, int *grid, int *block, size_t *lds,
-                            int *lds_stride, LaunchShape *used)
+// Launch shape. Each wave needs two LDS tally buffers; a workgroup uses at
+// most kLdsLimit. Unless the caller fixed them, the workgroup size (1, 2, 4 or
+// 8 waves) is the one that keeps the most waves resident per compute unit
+// (occupancy query; larger workgroups win ties) and the persistent grid holds
+// as many workgroups as the compute units keep resident at once.
+static cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
+                            size_t *lds, int *lds_stride, LaunchShape *used)
 {
     LaunchShape s = current_shape();
     int kp = max_bins + 1;
     kp += kp & 1;
-    const size_t per_wave = 2u * (size_t)kp * sizeof(double);
-    int waves = s.waves_per_block;
+    const size_t per_wave = (2u * (size_t)kp + kWaveExtraDoubles) * sizeof(double);
     const size_t limit = std::min(kLdsLimit, di.lds_per_block ? di.lds_per_block : kLdsLimit);
-    while (waves > 1 && per_wave * (size_t)waves > limit) --waves;
-    if (per_wave * (size_t)waves > limit) return fail(CLS_ERR_INVALID_ARG, "flux mesh too large for LDS");
-    *block = waves * 64;
-    *grid = di.cus * s.blocks_per_cu;
-    *lds = per_wave * (size_t)waves;
+    if (per_wave > limit) return fail(CLS_ERR_INVALID_ARG, "flux mesh too large for LDS");
+    int best_waves = 0, best_bpc = 0;
+    const int candidates[4] = {8, 4, 2, 1};
+    for (int c : candidates) {
+        if (s.waves_per_block > 0 && c != s.waves_per_block) continue;
+        if (per_wave * (size_t)c > limit) continue;
+        int bpc = s.blocks_per_cu;
+        if (bpc <= 0) {
+            const hipError_t e = track_occupancy(v, c * 64, per_wave * (size_t)c, &bpc);
+            if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        }
+        if (bpc * c > best_bpc * best_waves) { best_waves = c; best_bpc = bpc; }
+    }
+    if (best_waves == 0) {   // a fixed workgroup size that does not fit: shrink it
+        best_waves = s.waves_per_block;
+        while (best_waves > 1 && per_wave * (size_t)best_waves > limit) --best_waves;
+        best_bpc = s.blocks_per_cu;
+        if (best_bpc <= 0) {
+            const hipError_t e = track_occupancy(v, best_waves * 64, per_wave * (size_t)best_waves, &best_bpc);
+            if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+        }
+    }
+    best_bpc = std::max(best_bpc, 1);
+    *block = best_waves * 64;
+    *lds = per_wave * (size_t)best_waves;
     *lds_stride = kp;
-    s.waves_per_block = waves;
+    *grid = di.cus * best_bpc;
+    s.waves_per_block = best_waves;
+    s.blocks_per_cu = best_bpc;
     *used = s;
     return CLS_OK;
 }
@@ -449,7 +483,7 @@ cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed)
     int grid, block, stride;
     size_t lds;
     LaunchShape used;
-    st = shape_for(p->nbins, di, &grid, &block, &lds, &stride, &used);
+    st = shape_for(variant_of(p), p->nbins, di, &grid, &block, &lds, &stride, &used);
     if (st != CLS_OK) return st;
     const uint64_t waves_total = (uint64_t)grid * (uint64_t)(block / 64);
     const uint64_t chunk = chunk_size(histories, waves_total, (uint64_t)used.max_chunk);
@@ -519,7 +553,7 @@ cls_status cls_read_tallies(const cls_problem *p, cls_tallies *out, double *flux
     if (!p->has_run) return fail(CLS_ERR_STATE, "no completed run");
     if ((flux || flux_sigma) && nbins != p->nbins) return fail(CLS_ERR_INVALID_ARG, "nbins does not match the problem");
     hipError_t e = hipEventQuery(p->ev_done);
-    if (e == hipErrorNotReady) return CLS_ERR_NOT_READY;
+    if (e == hipErrorNotReady) return fail(CLS_ERR_NOT_READY, "the last run has not completed");
     if (e != hipSuccess) return hip_fail(e, "hipEventQuery");
     const uint64_t *C = p->h_record;
     const double *Rz = (const double *)(p->h_record + C_COUNT);
@@ -648,7 +682,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     int grid, block, stride;
     size_t lds;
     LaunchShape used;
-    st = shape_for(max_bins, di, &grid, &block, &lds, &stride, &used);
+    st = shape_for(variant_of(problems[0]), max_bins, di, &grid, &block, &lds, &stride, &used);
     if (st != CLS_OK) return st;
     const size_t probs_bytes = align256((size_t)n * sizeof(DevProblem));
     const size_t items_bytes = align256(((size_t)n + 2) * sizeof(uint64_t));
@@ -689,6 +723,9 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     HIP_TRY(hipEventRecord(bs->k1, s));
     HIP_TRY(launch_finalize(d_probs, n, s));
     HIP_TRY(hipMemcpyAsync(h_rec, d_rec, rec_words * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    // completion events of every problem precede the batch event on the stream,
+    // so they have all fired once the batch event has
+    for (int i = 0; i < n; ++i) HIP_TRY(hipEventRecord(problems[i]->ev_done, s));
     HIP_TRY(hipEventRecord(bs->done, s));
     HIP_TRY(hipEventSynchronize(bs->done));
     float ms = 0.0f;
@@ -699,7 +736,6 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
         cls_problem *p = problems[i];
         std::memcpy(p->h_record, h_rec + off, record_words(p->nbins) * sizeof(uint64_t));
         off += record_words(p->nbins);
-        HIP_TRY(hipEventRecord(p->ev_done, s));
         p->has_run = true;
         p->timed_by_events = false;
         p->track_ms = ms;

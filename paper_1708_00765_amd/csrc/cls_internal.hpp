@@ -43,6 +43,10 @@ struct alignas(16) DevProblem {
     double L, inv_dx, dx;
     double sigma[2], c[2], lam[2];
     double p0;                  // Lambda_0 / (Lambda_0 + Lambda_1)
+    double isig[2];             // 1 / Sigma_i
+    // FP32 copies for the FP32 tracking kernel
+    float Lf, p0f;
+    float isigf[2], cf[2], lamf[2];
     uint64_t seed;
     uint64_t histories;
     uint64_t chunk;             // histories per work item (batch)
@@ -66,6 +70,11 @@ struct TrackArgs {
     int lds_stride;              // doubles per tally buffer (>= max nbins + 1, even)
 };
 
+// LDS per wave beyond its two tally buffers: score sums of the two slots
+// (4 doubles) and kSlotCounters 32-bit counters per slot.
+constexpr int kSlotCounters = 12;
+constexpr int kWaveExtraDoubles = 4 + kSlotCounters;
+
 struct LaunchShape {
     int waves_per_block;
     int blocks_per_cu;
@@ -85,5 +94,8 @@ hipError_t launch_reset(const DevProblem *d_probs, int nprobs, uint64_t *queue_h
 hipError_t launch_track(const Variant &v, const TrackArgs &args, int grid, int block,
                         size_t lds_bytes, hipStream_t stream);
 hipError_t launch_finalize(const DevProblem *d_probs, int nprobs, hipStream_t stream);
+// Resident workgroups per compute unit of the tracking kernel for a block of
+// `block` threads with `lds_bytes` of dynamic LDS.
+hipError_t track_occupancy(const Variant &v, int block, size_t lds_bytes, int *blocks_per_cu);
 
 }  // namespace cls

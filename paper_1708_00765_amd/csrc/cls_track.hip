@@ -117,7 +117,257 @@ __device__ __forceinline__ uint64_t fnv_event(uint64_t h, int ev, int m, int bin
 // per-slot bookkeeping (wave-uniform values)
 // ---------------------------------------------------------------------------
 enum SlotCtr : int { S_T = 0, S_R, S_A, S_CAP, S_FLIGHTS, S_COLL, S_SCAT, S_INT, S_LAT, S_NCTR };
+static_assert(S_NCTR <= kSlotCounters, "slot counters do not fit their LDS area");
 
+// Problem parameters used by an event step. Loaded each step: with scalar
+// loads (SGPRs) when every live lane of the wave tracks the same problem, per
+// lane otherwise (a wave straddling two work chunks of different problems).
+template <typename R>
+struct Prm {
+    R isig0, isig1, c0, c1, lam0, lam1, p0, Lr;
+    double Ld, inv_dx, dx;
+    int K;
+    uint32_t key_lo, key_hi;
+    uint64_t trace_n, max_steps;
+    uint64_t *trace_hash;
+    uint32_t *trace_len;
+};
+
+template <typename R>
+__device__ __forceinline__ Prm<R> load_prm(const DevProblem &P)
+{
+    Prm<R> q;
+    if constexpr (std::is_same<R, float>::value) {
+        q.isig0 = P.isigf[0]; q.isig1 = P.isigf[1];
+        q.c0 = P.cf[0]; q.c1 = P.cf[1];
+        q.lam0 = P.lamf[0]; q.lam1 = P.lamf[1];
+        q.p0 = P.p0f; q.Lr = P.Lf;
+    } else {
+        q.isig0 = P.isig[0]; q.isig1 = P.isig[1];
+        q.c0 = P.c[0]; q.c1 = P.c[1];
+        q.lam0 = P.lam[0]; q.lam1 = P.lam[1];
+        q.p0 = P.p0; q.Lr = P.L;
+    }
+    q.Ld = P.L; q.inv_dx = P.inv_dx; q.dx = P.dx; q.K = P.nbins;
+    q.key_lo = (uint32_t)P.seed; q.key_hi = (uint32_t)(P.seed >> 32);
+    q.trace_n = P.trace_n; q.max_steps = P.max_steps;
+    q.trace_hash = P.trace_hash; q.trace_len = P.trace_len;
+    return q;
+}
+
+// Per-lane particle state.
+template <typename R>
+struct Lane {
+    double x;
+    R y, z, ux, uy, uz;
+    R iux, iuy, iuz, ig;     // cached 1/u components and 1/(chord factor)
+    double tscore;           // this history's flux score
+    uint64_t h;
+    uint64_t hash;
+    uint32_t step;
+    uint32_t n_int, n_scat, n_lat;   // this history's interface crossings, scatters, lateral reflections
+    int m, slot, pid, kcur;  // material, chunk slot, problem, bin of x
+    bool alive;
+};
+
+__device__ __forceinline__ int bin_index(double x, double inv_dx, int K)
+{
+    // truncation equals floor for x >= 0; slightly negative x maps to bin 0
+    const int k = (int)(x * inv_dx);
+    return k < K - 1 ? (k > 0 ? k : 0) : K - 1;
+}
+
+// One event step of one lane: the source (step 0) or a flight. Returns the
+// event code. `tal` is the lane's LDS tally buffer.
+template <int G, int EST, int SRC, bool FP32, bool TRACE, typename R>
+__device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *tal)
+{
+    using MM = Math<R>;
+    constexpr int AXES = (G == GEOM_EXT2D) ? 2 : (G == GEOM_CUBE3D ? 3 : 1);
+    constexpr bool DIR3 = (G == GEOM_EXT2D || G == GEOM_CUBE3D);
+    const R INF = (R)__builtin_huge_val();
+
+    const Block5 B = philox_u23(L.step, 0u, L.h, P.key_lo, P.key_hi);
+    int ev;
+    bool need_dir = false, src_dir = false;
+    R cos_t = 0, turns = 0;
+    if (L.step == 0) {
+        // ---- source (Section 2; Sec. 4.1-4.3) ----
+        L.m = (unit<R>(B.k[0]) < P.p0) ? 0 : 1;
+        L.x = 0.0; L.y = 0; L.z = 0;
+        if (SRC == SRC_FACE) {
+            if (G == GEOM_ROD) {
+                L.ux = 1; L.iux = 1;
+            } else if (G == GEOM_SLAB) {
+                L.ux = MM::sqrt_(unit<R>(B.k[1]));
+                L.iux = MM::rcp(L.ux);
+                L.ig = L.iux;
+            } else {
+                need_dir = true; src_dir = true;
+                cos_t = MM::sqrt_(unit<R>(B.k[1]));
+                turns = unit<R>(B.k[2]);
+                L.y = P.Lr * unit<R>(B.k[3]);
+                if (G == GEOM_CUBE3D) L.z = P.Lr * unit<R>(B.k[4]);
+            }
+        } else {
+            L.x = P.Ld * (double)unit<R>(B.k[1]);
+            if (G == GEOM_ROD) {
+                L.ux = unit<R>(B.k[2]) < (R)0.5 ? (R)1 : (R)-1;
+                L.iux = L.ux;
+            } else if (G == GEOM_SLAB) {
+                L.ux = (R)2 * unit<R>(B.k[2]) - (R)1;
+                L.iux = MM::rcp(L.ux);
+                L.ig = L.iux < 0 ? -L.iux : L.iux;
+            } else if (G == GEOM_EXT2D) {
+                L.y = P.Lr * unit<R>(B.k[2]);
+                need_dir = true;
+                cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
+                turns = unit<R>(B.k[4]);
+            } else {
+                need_dir = true;
+                cos_t = (R)2 * unit<R>(B.k[2]) - (R)1;
+                turns = unit<R>(B.k[3]);
+                L.y = P.Lr * unit<R>(B.k[4]);
+                const Block5 B2 = philox_u23(0u, 1u, L.h, P.key_lo, P.key_hi);
+                L.z = P.Lr * unit<R>(B2.k[0]);
+            }
+        }
+        L.kcur = bin_index(L.x, P.inv_dx, P.K);
+        ev = EV_SOURCE;
+        if (TRACE) L.hash = fnv_event(L.hash, EV_SOURCE, L.m, L.kcur);
+    } else if ((uint64_t)L.step > P.max_steps) {
+        ev = EV_CAP;
+        if (TRACE) L.hash = fnv_event(L.hash, EV_CAP, L.m, L.kcur);
+    } else {
+        // ---- flight: three distances, the smallest wins (Section 4) ----
+        const int mf = L.m;
+        const R isig_m = mf ? P.isig1 : P.isig0;
+        const R lam_m = mf ? P.lam1 : P.lam0;
+        const R lc = MM::neglog(unit<R>(B.k[0])) * isig_m;
+        const R li = MM::neglog(unit<R>(B.k[1])) * lam_m * L.ig;
+        R lb;
+        int face;
+        {
+            const double dxf = L.ux > 0 ? (P.Ld - L.x) : (0.0 - L.x);
+            lb = (L.ux == 0) ? INF : (R)dxf * L.iux;
+            face = L.ux > 0 ? 1 : 0;
+        }
+        if (AXES >= 2) {
+            const R d = L.uy > 0 ? (P.Lr - L.y) : (R)0 - L.y;
+            const R l = (L.uy == 0) ? INF : d * L.iuy;
+            if (l < lb) { lb = l; face = L.uy > 0 ? 3 : 2; }
+        }
+        if (AXES >= 3) {
+            const R d = L.uz > 0 ? (P.Lr - L.z) : (R)0 - L.z;
+            const R l = (L.uz == 0) ? INF : d * L.iuz;
+            if (l < lb) { lb = l; face = L.uz > 0 ? 5 : 4; }
+        }
+        const bool bnd = (lb <= lc) && (lb <= li);
+        const bool coll = !bnd && (lc <= li);
+        R s = bnd ? lb : (coll ? lc : li);
+        if (FP32) s = s > (R)0 ? s : (R)0;      // l_b <= 0: cross at once
+        const double xa = L.x;
+        const int ka0 = L.kcur;
+        L.x += (double)(s * L.ux);
+        if (AXES >= 2) L.y += s * L.uy;
+        if (AXES >= 3) L.z += s * L.uz;
+        if (bnd) {
+            const R fv = (face & 1) ? P.Lr : (R)0;
+            if (face < 2) L.x = (face & 1) ? P.Ld : 0.0;
+            else if (face < 4) L.y = fv;
+            else L.z = fv;
+        }
+        if (FP32) {
+            L.x = L.x < 0.0 ? 0.0 : (L.x > P.Ld ? P.Ld : L.x);
+            if (AXES >= 2) L.y = L.y < (R)0 ? (R)0 : (L.y > P.Lr ? P.Lr : L.y);
+            if (AXES >= 3) L.z = L.z < (R)0 ? (R)0 : (L.z > P.Lr ? P.Lr : L.z);
+        }
+        L.kcur = bin_index(L.x, P.inv_dx, P.K);
+        // ---- track-length score in difference form ----
+        if (EST == EST_TRACK) {
+            const double sd = (double)s;
+            if (sd > 0.0) {
+                L.tscore += sd;
+                const bool up = L.x >= xa;
+                const int ka = up ? ka0 : L.kcur;
+                const int kb = up ? L.kcur : ka0;
+                if (ka == kb) {
+                    lds_add(tal + ka, sd);
+                    lds_add(tal + ka + 1, -sd);
+                } else {
+                    const double lo = up ? xa : L.x;
+                    const double hi = up ? L.x : xa;
+                    const double w = (double)(L.iux < 0 ? -L.iux : L.iux);
+                    const double pa = ((double)(ka + 1) * P.dx - lo) * w;
+                    const double pb = (hi - (double)kb * P.dx) * w;
+                    const double full = P.dx * w;
+                    lds_add(tal + ka, pa);
+                    lds_add(tal + ka + 1, full - pa);
+                    lds_add(tal + kb, pb - full);
+                    lds_add(tal + kb + 1, -pb);
+                }
+            }
+        }
+        // ---- the event ----
+        if (bnd) {
+            if (face == 0) ev = EV_LEAK_XLO;
+            else if (face == 1) ev = EV_LEAK_XHI;
+            else {
+                ev = EV_REFL_YLO + (face - 2);
+                if (face < 4) { L.uy = -L.uy; L.iuy = -L.iuy; }
+                else { L.uz = -L.uz; L.iuz = -L.iuz; }
+            }
+        } else if (!coll) {
+            ev = EV_INTERFACE;
+            L.m = 1 - mf;
+        } else {
+            if (EST == EST_COLLISION) {
+                lds_add(tal + L.kcur, (double)isig_m);
+                L.tscore += (double)isig_m;
+            }
+            const R c_m = mf ? P.c1 : P.c0;
+            if (unit<R>(B.k[2]) < c_m) {
+                ev = EV_SCATTER;
+                if (G == GEOM_ROD) {
+                    L.ux = unit<R>(B.k[3]) < (R)0.5 ? (R)1 : (R)-1;
+                    L.iux = L.ux;
+                } else if (G == GEOM_SLAB) {
+                    L.ux = (R)2 * unit<R>(B.k[3]) - (R)1;
+                    L.iux = MM::rcp(L.ux);
+                    L.ig = L.iux < 0 ? -L.iux : L.iux;
+                } else {
+                    need_dir = true;
+                    cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
+                    turns = unit<R>(B.k[4]);
+                }
+            } else {
+                ev = EV_ABSORB;
+            }
+        }
+        L.n_int += (ev == EV_INTERFACE);
+        L.n_scat += (ev == EV_SCATTER);
+        if (AXES >= 2) L.n_lat += (ev >= EV_REFL_YLO);
+        if (TRACE) L.hash = fnv_event(L.hash, ev, mf, L.kcur);
+    }
+    // ---- shared direction sampler: polar axis x for the inward cosine-law
+    //      source, z for isotropic emission ----
+    if (DIR3 && need_dir) {
+        R sn, cs;
+        MM::sincos_turns(turns, &sn, &cs);
+        R st;
+        if (FP32) st = MM::sqrt_(((R)1 - cos_t) * ((R)1 + cos_t));
+        else st = MM::sqrt_((R)1 - cos_t * cos_t);
+        const R a = st * cs, b = st * sn;
+        if (src_dir) { L.ux = cos_t; L.uy = a; L.uz = b; }
+        else { L.ux = a; L.uy = b; L.uz = cos_t; }
+        L.iux = MM::rcp(L.ux);
+        L.iuy = MM::rcp(L.uy);
+        L.iuz = MM::rcp(L.uz);
+        if (G == GEOM_EXT2D) L.ig = MM::rsqrt(L.ux * L.ux + L.uy * L.uy);
+    }
+    ++L.step;
+    return ev;
+}
 
 // ---------------------------------------------------------------------------
 // the tracking kernel
@@ -126,63 +376,37 @@ template <int G, int EST, int SRC, bool FP32, bool TRACE>
 __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
 {
     using R = typename std::conditional<FP32, float, double>::type;
-    using MM = Math<R>;
-    constexpr int AXES = (G == GEOM_EXT2D) ? 2 : (G == GEOM_CUBE3D ? 3 : 1);
-    constexpr bool DIR3 = (G == GEOM_EXT2D || G == GEOM_CUBE3D);
-    const R INF = (R)__builtin_huge_val();
 
     extern __shared__ double lds[];
     const int lane = (int)(threadIdx.x & 63u);
     const int wid = (int)(threadIdx.x >> 6);
     const int KP = A.lds_stride;
-    double *const wbuf = lds + (size_t)wid * 2u * (size_t)KP;
-    for (int i = lane; i < 2 * KP; i += 64) wbuf[i] = 0.0;
+    // per wave: two tally buffers of KP doubles, then the score sum and score
+    // square sum of each slot, then kSlotCounters 32-bit counters per slot
+    double *const wbuf = lds + (size_t)wid * (2u * (size_t)KP + kWaveExtraDoubles);
+    double *const wsum = wbuf + 2 * KP;
+    uint32_t *const wctr = (uint32_t *)(wsum + 4);    // [slot][kSlotCounters]
+    for (int i = lane; i < 2 * KP + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
 
     // Wave-uniform state of the two chunk slots: first history, size,
-    // histories handed out, histories in flight, problem, open flag, counters.
+    // histories handed out, histories in flight, problem, open flag.
     uint64_t s_h0[2] = {0, 0};
     uint32_t s_cnt[2] = {0, 0}, s_next[2] = {0, 0}, s_live[2] = {0, 0};
     int32_t s_pid[2] = {0, 0}, s_open[2] = {0, 0};
-    uint32_t ctr[2][S_NCTR];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < S_NCTR; ++i) ctr[s][i] = 0;
     int cur = 0;
     bool queue_empty = false;
     const uint64_t total_items = A.item_start[A.nprobs];
 
-    // lane state
-    bool alive = false;
-    int slot = 0;
-    uint64_t h = 0;
-    uint32_t step = 0;
-    int m = 0;
-    double x = 0.0;
-    R y = 0, z = 0, ux = 0, uy = 0, uz = 0;
-    R iux = 0, iuy = 0, iuz = 0, ig = 1;   // cached 1/u components and 1/chord factor
-    double tscore = 0.0;
-    uint64_t hash = 0;
-    // lane copy of its problem's parameters
-    R sig0 = 1, sig1 = 1, isig0 = 1, isig1 = 1, c0 = 0, c1 = 0, lam0 = 1, lam1 = 1, p0 = 0;
-    R Lr = 1;
-    double Ld = 1.0, inv_dx = 1.0, dx = 1.0;
-    int K = 1;
-    uint32_t key_lo = 0, key_hi = 0;
-    uint64_t trace_n = 0, max_steps = 0;
-    uint64_t *trace_hash = nullptr;
-    uint32_t *trace_len = nullptr;
-    double acc_t[2] = {0.0, 0.0}, acc_t2[2] = {0.0, 0.0};
-
-    auto bin_of = [&](double xx) -> int {
-        int k = (int)floor(xx * inv_dx);
-        k = k < 0 ? 0 : k;
-        return k > K - 1 ? K - 1 : k;
-    };
+    Lane<R> L;
+    L.x = 0.0; L.y = L.z = L.ux = L.uy = L.uz = 0;
+    L.iux = L.iuy = L.iuz = 0; L.ig = 1;
+    L.tscore = 0.0; L.h = 0; L.hash = 0; L.step = 0;
+    L.n_int = L.n_scat = L.n_lat = 0;
+    L.m = 0; L.slot = 0; L.pid = 0; L.kcur = 0; L.alive = false;
 
     for (;;) {
         // ---------------- hand out histories to idle lanes ----------------
-        uint64_t dead = ballot(!alive);
+        uint64_t dead = ballot(!L.alive);
         while (dead != 0) {
             if (!s_open[cur] || s_next[cur] == s_cnt[cur]) {
                 const int o = cur ^ 1;
@@ -208,13 +432,6 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                 s_live[o] = 0;
                 s_pid[o] = lo;
                 s_open[o] = 1;
-                if (o) {
-#pragma unroll
-                    for (int i = 0; i < S_NCTR; ++i) ctr[1][i] = 0;
-                } else {
-#pragma unroll
-                    for (int i = 0; i < S_NCTR; ++i) ctr[0][i] = 0;
-                }
                 cur = o;
                 continue;
             }
@@ -222,247 +439,69 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             const uint32_t nd = popc(dead);
             const uint32_t take = avail < nd ? avail : nd;
             const uint32_t r = rank_in(dead);
-            if (!alive && r < take) {
-                const DevProblem &P = A.probs[s_pid[cur]];
-                alive = true;
-                slot = cur;
-                h = s_h0[cur] + s_next[cur] + r;
-                step = 0;
-                tscore = 0.0;
-                hash = 0xCBF29CE484222325ull;
-                sig0 = (R)P.sigma[0]; sig1 = (R)P.sigma[1];
-                isig0 = MM::rcp(sig0); isig1 = MM::rcp(sig1);
-                c0 = (R)P.c[0]; c1 = (R)P.c[1];
-                lam0 = (R)P.lam[0]; lam1 = (R)P.lam[1];
-                p0 = (R)P.p0;
-                Ld = P.L; Lr = (R)P.L;
-                inv_dx = P.inv_dx; dx = P.dx;
-                K = P.nbins;
-                key_lo = (uint32_t)P.seed; key_hi = (uint32_t)(P.seed >> 32);
-                trace_n = P.trace_n; trace_hash = P.trace_hash; trace_len = P.trace_len;
-                max_steps = P.max_steps;
+            if (!L.alive && r < take) {
+                L.alive = true;
+                L.slot = cur;
+                L.pid = s_pid[cur];
+                L.h = s_h0[cur] + s_next[cur] + r;
+                L.step = 0;
+                L.n_int = L.n_scat = L.n_lat = 0;
+                L.tscore = 0.0;
+                L.hash = 0xCBF29CE484222325ull;
             }
             s_next[cur] += take;
             s_live[cur] += take;
-            dead = ballot(!alive);
+            dead = ballot(!L.alive);
         }
 
         // ---------------- exit when nothing is left --------------------------
         if (dead == ~0ull && queue_empty && !s_open[0] && !s_open[1]) break;
 
         // ---------------- one event step per live lane -----------------------
+        // A wave holds lanes of at most two problems (one per slot); each pass
+        // steps the lanes of one problem with its parameters in scalars.
         int ev = EV_NONE;
-        if (alive) {
-            const Block5 B = philox_u23(step, 0u, h, key_lo, key_hi);
-            bool need_dir = false;
-            bool src_dir = false;
-            R cos_t = 0, turns = 0;
-            double xa = 0.0;
-            if (step == 0) {
-                // ---- source (Section 2, Sec. 4.1-4.3) ----
-                m = (unit<R>(B.k[0]) < p0) ? 0 : 1;
-                x = 0.0; y = 0; z = 0;
-                if (SRC == SRC_FACE) {
-                    if (G == GEOM_ROD) {
-                        ux = 1; iux = 1;
-                    } else if (G == GEOM_SLAB) {
-                        ux = MM::sqrt_(unit<R>(B.k[1]));
-                        iux = MM::rcp(ux);
-                        ig = iux;
-                    } else {
-                        need_dir = true; src_dir = true;
-                        cos_t = MM::sqrt_(unit<R>(B.k[1]));
-                        turns = unit<R>(B.k[2]);
-                        y = Lr * unit<R>(B.k[3]);
-                        if (G == GEOM_CUBE3D) z = Lr * unit<R>(B.k[4]);
-                    }
-                } else {
-                    x = Ld * (double)unit<R>(B.k[1]);
-                    if (G == GEOM_ROD) {
-                        ux = unit<R>(B.k[2]) < (R)0.5 ? (R)1 : (R)-1;
-                        iux = ux;
-                    } else if (G == GEOM_SLAB) {
-                        ux = (R)2 * unit<R>(B.k[2]) - (R)1;
-                        iux = MM::rcp(ux);
-                        ig = iux < 0 ? -iux : iux;
-                    } else if (G == GEOM_EXT2D) {
-                        y = Lr * unit<R>(B.k[2]);
-                        need_dir = true;
-                        cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
-                        turns = unit<R>(B.k[4]);
-                    } else {
-                        need_dir = true;
-                        cos_t = (R)2 * unit<R>(B.k[2]) - (R)1;
-                        turns = unit<R>(B.k[3]);
-                        y = Lr * unit<R>(B.k[4]);
-                        const Block5 B2 = philox_u23(0u, 1u, h, key_lo, key_hi);
-                        z = Lr * unit<R>(B2.k[0]);
-                    }
-                }
-                ev = EV_SOURCE;
-                if (TRACE) hash = fnv_event(hash, EV_SOURCE, m, bin_of(x));
-            } else if ((uint64_t)step > max_steps) {
-                ev = EV_CAP;
-                if (TRACE) hash = fnv_event(hash, EV_CAP, m, bin_of(x));
-            } else {
-                // ---- flight ----
-                const R sig_m = m ? sig1 : sig0;
-                const R isig_m = m ? isig1 : isig0;
-                const R lam_m = m ? lam1 : lam0;
-                const R lc = MM::neglog(unit<R>(B.k[0])) * isig_m;
-                const R li = MM::neglog(unit<R>(B.k[1])) * lam_m * ig;
-                // distance to the boundary; ties go to x, then y, then z
-                R lb;
-                int face;
-                {
-                    const double dxf = ux > 0 ? (Ld - x) : (0.0 - x);
-                    lb = (ux == 0) ? INF : (R)dxf * iux;
-                    face = ux > 0 ? 1 : 0;
-                }
-                if (AXES >= 2) {
-                    const R d = uy > 0 ? (Lr - y) : (R)0 - y;
-                    const R l = (uy == 0) ? INF : d * iuy;
-                    if (l < lb) { lb = l; face = uy > 0 ? 3 : 2; }
-                }
-                if (AXES >= 3) {
-                    const R d = uz > 0 ? (Lr - z) : (R)0 - z;
-                    const R l = (uz == 0) ? INF : d * iuz;
-                    if (l < lb) { lb = l; face = uz > 0 ? 5 : 4; }
-                }
-                const bool bnd = (lb <= lc) && (lb <= li);
-                const bool coll = !bnd && (lc <= li);
-                R s = bnd ? lb : (coll ? lc : li);
-                if (FP32) s = s > (R)0 ? s : (R)0;   // l_b <= 0: cross at once
-                xa = x;
-                x += (double)(s * ux);
-                if (AXES >= 2) y += s * uy;
-                if (AXES >= 3) z += s * uz;
-                if (bnd) {
-                    const R fv = (face & 1) ? Lr : (R)0;
-                    if (face < 2) x = (face & 1) ? Ld : 0.0;
-                    else if (face < 4) y = fv;
-                    else z = fv;
-                }
-                if (FP32) {
-                    x = x < 0.0 ? 0.0 : (x > Ld ? Ld : x);
-                    if (AXES >= 2) y = y < (R)0 ? (R)0 : (y > Lr ? Lr : y);
-                    if (AXES >= 3) z = z < (R)0 ? (R)0 : (z > Lr ? Lr : z);
-                }
-                // ---- track-length score in difference form ----
-                const double sd = (double)s;
-                if (EST == EST_TRACK && sd > 0.0) {
-                    double *b = wbuf + slot * KP;
-                    const double lo = xa < x ? xa : x;
-                    const double hi = xa < x ? x : xa;
-                    const int ka = bin_of(lo);
-                    const int kb = bin_of(hi);
-                    tscore += sd;
-                    if (ka == kb) {
-                        lds_add(b + ka, sd);
-                        lds_add(b + ka + 1, -sd);
-                    } else {
-                        const double w = (double)(iux < 0 ? -iux : iux);
-                        const double pa = ((double)(ka + 1) * dx - lo) * w;
-                        const double pb = (hi - (double)kb * dx) * w;
-                        const double full = dx * w;
-                        lds_add(b + ka, pa);
-                        lds_add(b + ka + 1, full - pa);
-                        lds_add(b + kb, pb - full);
-                        lds_add(b + kb + 1, -pb);
-                    }
-                }
-                const int mf = m;
-                if (bnd) {
-                    if (face == 0) ev = EV_LEAK_XLO;
-                    else if (face == 1) ev = EV_LEAK_XHI;
-                    else {
-                        ev = EV_REFL_YLO + (face - 2);
-                        if (face < 4) { uy = -uy; iuy = -iuy; }
-                        else { uz = -uz; iuz = -iuz; }
-                    }
-                } else if (!coll) {
-                    ev = EV_INTERFACE;
-                    m = 1 - m;
-                } else {
-                    const int k = bin_of(x);
-                    if (EST == EST_COLLISION) {
-                        lds_add(wbuf + slot * KP + k, (double)isig_m);
-                        tscore += (double)isig_m;
-                    }
-                    const R c_m = mf ? c1 : c0;
-                    if (unit<R>(B.k[2]) < c_m) {
-                        ev = EV_SCATTER;
-                        if (G == GEOM_ROD) {
-                            ux = unit<R>(B.k[3]) < (R)0.5 ? (R)1 : (R)-1;
-                            iux = ux;
-                        } else if (G == GEOM_SLAB) {
-                            ux = (R)2 * unit<R>(B.k[3]) - (R)1;
-                            iux = MM::rcp(ux);
-                            ig = iux < 0 ? -iux : iux;
-                        } else {
-                            need_dir = true;
-                            cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
-                            turns = unit<R>(B.k[4]);
-                        }
-                    } else {
-                        ev = EV_ABSORB;
-                    }
-                }
-                (void)sig_m;
-                if (TRACE) hash = fnv_event(hash, ev, mf, bin_of(x));
+        uint64_t todo = ballot(L.alive);
+        while (todo != 0) {
+            const int first = __builtin_ctzll(todo);
+            const int pidc = __shfl(L.pid, first, 64);
+            const bool mine = L.alive && L.pid == pidc && ((todo >> lane) & 1ull);
+            if (mine) {
+                const Prm<R> P = load_prm<R>(A.probs[__builtin_amdgcn_readfirstlane(pidc)]);
+                ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + L.slot * KP);
             }
-            // ---- shared direction sampler: polar axis x for the inward
-            //      cosine-law source, z for isotropic emission ----
-            if (DIR3 && need_dir) {
-                R sn, cs;
-                MM::sincos_turns(turns, &sn, &cs);
-                R st;
-                if (FP32) st = MM::sqrt_(((R)1 - cos_t) * ((R)1 + cos_t));
-                else st = MM::sqrt_((R)1 - cos_t * cos_t);
-                const R a = st * cs, b = st * sn;
-                if (src_dir) { ux = cos_t; uy = a; uz = b; }
-                else { ux = a; uy = b; uz = cos_t; }
-                iux = MM::rcp(ux);
-                iuy = MM::rcp(uy);
-                iuz = MM::rcp(uz);
-                if (G == GEOM_EXT2D) ig = MM::rsqrt(ux * ux + uy * uy);
-            }
-            ++step;
+            todo &= ~ballot(mine);
         }
 
-        // ---------------- wave-level tallies ---------------------------------
+        // ---------------- histories that ended -------------------------------
         const bool fin = (ev == EV_LEAK_XLO) || (ev == EV_LEAK_XHI) || (ev == EV_ABSORB) || (ev == EV_CAP);
-        const uint64_t in1 = ballot(alive && slot == 1);      // lanes of slot 1 (before retiring)
-        const uint64_t flights = ballot(ev != EV_NONE && ev != EV_SOURCE && ev != EV_CAP);
-        const uint64_t m_int = ballot(ev == EV_INTERFACE);
-        const uint64_t m_coll = ballot(ev == EV_SCATTER || ev == EV_ABSORB);
-        const uint64_t m_scat = ballot(ev == EV_SCATTER);
-        const uint64_t m_lat = ballot(ev >= EV_REFL_YLO && ev <= EV_REFL_ZHI);
         const uint64_t m_fin = ballot(fin);
-        ctr[0][S_FLIGHTS] += popc(flights & ~in1);  ctr[1][S_FLIGHTS] += popc(flights & in1);
-        ctr[0][S_INT] += popc(m_int & ~in1);        ctr[1][S_INT] += popc(m_int & in1);
-        ctr[0][S_COLL] += popc(m_coll & ~in1);      ctr[1][S_COLL] += popc(m_coll & in1);
-        ctr[0][S_SCAT] += popc(m_scat & ~in1);      ctr[1][S_SCAT] += popc(m_scat & in1);
-        ctr[0][S_LAT] += popc(m_lat & ~in1);        ctr[1][S_LAT] += popc(m_lat & in1);
         if (m_fin) {
-            const uint64_t mT = ballot(ev == EV_LEAK_XHI);
-            const uint64_t mR = ballot(ev == EV_LEAK_XLO);
-            const uint64_t mA = ballot(ev == EV_ABSORB);
-            const uint64_t mC = ballot(ev == EV_CAP);
-            ctr[0][S_T] += popc(mT & ~in1);  ctr[1][S_T] += popc(mT & in1);
-            ctr[0][S_R] += popc(mR & ~in1);  ctr[1][S_R] += popc(mR & in1);
-            ctr[0][S_A] += popc(mA & ~in1);  ctr[1][S_A] += popc(mA & in1);
-            ctr[0][S_CAP] += popc(mC & ~in1); ctr[1][S_CAP] += popc(mC & in1);
+            const uint64_t in1 = ballot(fin && L.slot == 1);
             s_live[0] -= popc(m_fin & ~in1);
             s_live[1] -= popc(m_fin & in1);
             if (fin) {
-                if (slot) { acc_t[1] += tscore; acc_t2[1] += tscore * tscore; }
-                else { acc_t[0] += tscore; acc_t2[0] += tscore * tscore; }
-                if (TRACE && h < trace_n) {
-                    trace_hash[h] = hash;
-                    trace_len[h] = step - 1u;
+                double *ss = wsum + 2 * L.slot;
+                lds_add(ss, L.tscore);
+                lds_add(ss + 1, L.tscore * L.tscore);
+                uint32_t *c = wctr + L.slot * kSlotCounters;
+                const int outcome = ev == EV_LEAK_XHI ? S_T : (ev == EV_LEAK_XLO ? S_R : (ev == EV_ABSORB ? S_A : S_CAP));
+                atomicAdd(c + outcome, 1u);
+                // steps = source + flights (+ the refused step of a capped history)
+                const uint32_t flights = L.step - 1u - (ev == EV_CAP ? 1u : 0u);
+                atomicAdd(c + S_FLIGHTS, flights);
+                atomicAdd(c + S_COLL, L.n_scat + (ev == EV_ABSORB ? 1u : 0u));
+                atomicAdd(c + S_SCAT, L.n_scat);
+                atomicAdd(c + S_INT, L.n_int);
+                if (G == GEOM_EXT2D || G == GEOM_CUBE3D) atomicAdd(c + S_LAT, L.n_lat);
+                if (TRACE) {
+                    const DevProblem &P = A.probs[L.pid];
+                    if (L.h < P.trace_n) {
+                        P.trace_hash[L.h] = L.hash;
+                        P.trace_len[L.h] = flights;
+                    }
                 }
-                alive = false;
+                L.alive = false;
             }
 
             // ------------- flush chunks whose last history ended -------------
@@ -489,22 +528,21 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                         }
                         if (k <= KK) b[k] = 0.0;
                     }
-                    const double st = wave_sum(acc_t[s]);
-                    const double st2 = wave_sum(acc_t2[s]);
-                    acc_t[s] = 0.0;
-                    acc_t2[s] = 0.0;
+                    const double st = wsum[2 * s];
+                    const double st2 = wsum[2 * s + 1];
+                    uint32_t *c = wctr + s * kSlotCounters;
+                    // one counter per lane: lanes 0..S_NCTR-1 move them to HBM
+                    const uint32_t cv = lane < S_NCTR ? c[lane] : 0u;
+                    if (lane < S_NCTR) c[lane] = 0u;
+                    const int slot_ctr_to_global[S_NCTR] = {C_TRANSMITTED, C_REFLECTED, C_ABSORBED, C_CAPPED,
+                                                            C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_INTERFACES,
+                                                            C_LATERAL};
+                    unsigned long long *C = (unsigned long long *)P.counters;
+                    if (lane < S_NCTR && cv != 0u) atomicAdd(C + slot_ctr_to_global[lane], (unsigned long long)cv);
                     if (lane == 0) {
-                        unsigned long long *C = (unsigned long long *)P.counters;
+                        wsum[2 * s] = 0.0;
+                        wsum[2 * s + 1] = 0.0;
                         atomicAdd(C + C_HISTORIES, (unsigned long long)s_cnt[s]);
-                        atomicAdd(C + C_TRANSMITTED, (unsigned long long)ctr[s][S_T]);
-                        atomicAdd(C + C_REFLECTED, (unsigned long long)ctr[s][S_R]);
-                        atomicAdd(C + C_ABSORBED, (unsigned long long)ctr[s][S_A]);
-                        atomicAdd(C + C_CAPPED, (unsigned long long)ctr[s][S_CAP]);
-                        atomicAdd(C + C_FLIGHTS, (unsigned long long)ctr[s][S_FLIGHTS]);
-                        atomicAdd(C + C_COLLISIONS, (unsigned long long)ctr[s][S_COLL]);
-                        atomicAdd(C + C_SCATTERS, (unsigned long long)ctr[s][S_SCAT]);
-                        atomicAdd(C + C_INTERFACES, (unsigned long long)ctr[s][S_INT]);
-                        atomicAdd(C + C_LATERAL, (unsigned long long)ctr[s][S_LAT]);
                         atomicAdd(C + C_BATCHES, 1ull);
                         atomicAdd(P.sums + 0, st);
                         atomicAdd(P.sums + 1, st2);
@@ -591,44 +629,51 @@ hipError_t launch_finalize(const DevProblem *d_probs, int nprobs, hipStream_t st
     return hipGetLastError();
 }
 
-template <int G, int EST, int SRC, bool FP32, bool TRACE>
-static hipError_t launch_one(const TrackArgs &a, int grid, int block, size_t lds, hipStream_t s)
-{
-    hipLaunchKernelGGL((track_kernel<G, EST, SRC, FP32, TRACE>), dim3(grid), dim3(block), lds, s, a);
-    return hipGetLastError();
-}
+// Kernel entry for a variant: geometry x estimator x source x precision x trace.
+typedef void (*TrackFn)(TrackArgs);
 
 template <int G, int EST, int SRC>
-static hipError_t launch_prec(const Variant &v, const TrackArgs &a, int grid, int block, size_t lds,
-                              hipStream_t s)
+static TrackFn pick_prec(const Variant &v)
 {
-    if (v.fp32) return launch_one<G, EST, SRC, true, false>(a, grid, block, lds, s);
-    if (v.trace) return launch_one<G, EST, SRC, false, true>(a, grid, block, lds, s);
-    return launch_one<G, EST, SRC, false, false>(a, grid, block, lds, s);
+    if (v.fp32) return track_kernel<G, EST, SRC, true, false>;
+    if (v.trace) return track_kernel<G, EST, SRC, false, true>;
+    return track_kernel<G, EST, SRC, false, false>;
 }
 
 template <int G>
-static hipError_t launch_geom(const Variant &v, const TrackArgs &a, int grid, int block, size_t lds,
-                              hipStream_t s)
+static TrackFn pick_geom(const Variant &v)
 {
-    if (v.est == EST_TRACK) {
-        if (v.src == SRC_FACE) return launch_prec<G, EST_TRACK, SRC_FACE>(v, a, grid, block, lds, s);
-        return launch_prec<G, EST_TRACK, SRC_VOLUME>(v, a, grid, block, lds, s);
+    if (v.est == EST_TRACK)
+        return v.src == SRC_FACE ? pick_prec<G, EST_TRACK, SRC_FACE>(v) : pick_prec<G, EST_TRACK, SRC_VOLUME>(v);
+    return v.src == SRC_FACE ? pick_prec<G, EST_COLLISION, SRC_FACE>(v) : pick_prec<G, EST_COLLISION, SRC_VOLUME>(v);
+}
+
+static TrackFn pick(const Variant &v)
+{
+    switch (v.geom) {
+    case GEOM_ROD: return pick_geom<GEOM_ROD>(v);
+    case GEOM_SLAB: return pick_geom<GEOM_SLAB>(v);
+    case GEOM_EXT2D: return pick_geom<GEOM_EXT2D>(v);
+    case GEOM_CUBE3D: return pick_geom<GEOM_CUBE3D>(v);
+    default: return nullptr;
     }
-    if (v.src == SRC_FACE) return launch_prec<G, EST_COLLISION, SRC_FACE>(v, a, grid, block, lds, s);
-    return launch_prec<G, EST_COLLISION, SRC_VOLUME>(v, a, grid, block, lds, s);
+}
+
+hipError_t track_occupancy(const Variant &v, int block, size_t lds, int *blocks_per_cu)
+{
+    const TrackFn f = pick(v);
+    if (!f) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void *>(f),
+                                                        block, lds);
 }
 
 hipError_t launch_track(const Variant &v, const TrackArgs &a, int grid, int block, size_t lds,
                         hipStream_t s)
 {
-    switch (v.geom) {
-    case GEOM_ROD: return launch_geom<GEOM_ROD>(v, a, grid, block, lds, s);
-    case GEOM_SLAB: return launch_geom<GEOM_SLAB>(v, a, grid, block, lds, s);
-    case GEOM_EXT2D: return launch_geom<GEOM_EXT2D>(v, a, grid, block, lds, s);
-    case GEOM_CUBE3D: return launch_geom<GEOM_CUBE3D>(v, a, grid, block, lds, s);
-    default: return hipErrorInvalidValue;
-    }
+    const TrackFn f = pick(v);
+    if (!f || grid <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(f, dim3(grid), dim3(block), lds, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace cls

@@ -34,8 +34,9 @@ __device__ __forceinline__ Block5 philox_u23(uint32_t step, uint32_t lane, uint6
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)a * 0xD2511F53u;   // one v_mad_u64_u32 each
         const uint64_t pc = (uint64_t)c * 0xCD9E8D57u;
-        const uint32_t na = (uint32_t)(pc >> 32) ^ b ^ k0;
-        const uint32_t nc = (uint32_t)(pa >> 32) ^ d ^ k1;
+        // three-input XOR in one gfx950 bitop3 (truth table 0x96)
+        const uint32_t na = __builtin_amdgcn_bitop3_b32((uint32_t)(pc >> 32), b, k0, 0x96);
+        const uint32_t nc = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), d, k1, 0x96);
         b = (uint32_t)pc;
         d = (uint32_t)pa;
         a = na;

@@ -1,65 +1,101 @@
 """Algorithmic work model of CLS tracking on the CDNA vector ALU (VALU).
 
 CLS transport moves almost no data: a problem is ~10 scalars in and 2K doubles
-out, and a particle's state lives in registers. The bound is the VALU issue
-rate, so the roofline is counted in VALU issue slots: one slot = one wave64
-lane-operation at full rate; an operation with a quarter-rate pipe
-(transcendentals, 32x32 -> 64-bit integer multiply) costs 4 slots.
+out, and a particle's state lives in registers. The bound is VALU issue, so the
+roofline is counted in VALU issue slots.
 
-Peak: 256 compute units x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 slots/s
-(equivalently the FP32 vector peak of 157.3 TFLOP/s divided by 2 for packed
-issue and by 2 for the fused multiply-add).
+Peak (published): the FP32 vector rate of 157.3 TFLOP/s is 78.6e12 fused
+multiply-adds per second, i.e. 256 compute units x 128 lanes x 2.4 GHz. One
+slot = one lane-operation at that rate.
 
-Algorithmic slots per unit of work, counted from the operations the method
-needs (Algorithm A, Section 4 of arXiv 1708.00765) and nothing else -- no
-register moves, control flow, divergence or bookkeeping:
+Price of each operation class, in slots = peak / (its measured throughput),
+from the instruction-rate microbenchmarks (csrc/microbench.hip, results in
+profiles/microbench_gfx950.md): FP32 add/mul/fma 1.36; other 32-bit VALU
+operations (integer, compare, select, conversion, bit logic) 2.22; FP64
+add/mul/fma 2.41; FP32 transcendental (log2, sin, cos, sqrt, rcp, rsq) 4.5;
+one Philox4x32-10 block including the five 23-bit fields 88.6; FP64 log 188.5,
+sincos 125, sqrt 42.2, division/reciprocal 28.4.
 
-event step (every flight and every source sample), one Philox4x32-10 block:
-  10 rounds x (2 x 32x32->64 multiply [4 each] + 2 three-input XOR + 2 key adds) = 120
-  five 23-bit uniforms: 4 shifts + 3 bit-field ops + 5 int->float + 5 scale     =  17
-flight (in addition to the step):
-  material selection of 1/Sigma, Lambda, c                                       =   3
-  two -ln U (log2 [4] + scale [1] each) and the two distances                    =  12
-  distance to each face: subtract, scale, compare-select (4 per axis, +1 FP64)   =  4*axes + 1
-  minimum of three and event code                                                =   4
-  move (per axis one FMA; x in FP64) and boundary snap                           =  axes + 2
-  track-length score: two bin indices (3 each), partial overlaps (6),
-  four LDS addresses (4)                                                         =  16
-  event dispatch and material switch                                             =   3
-scatter (in addition to its flight), 3D and 2D:
-  mu = 2U - 1, sin and cos of 2 pi U [4 each], sqrt(1 - mu^2) [4 + 2],
-  two products, three reciprocals of the direction [4 each], 2D chord factor
-  (rsqrt [4] + 3)                                                                =  28 (3D), 35 (2D)
-source (in addition to its step): material choice, sqrt [4], sin/cos [8],
-  sqrt(1-U) [5], lateral positions, reciprocals [12]                             =  33
-lateral reflection: negate one direction component and its reciprocal          =   2
+Operation counts per unit of work are those the method needs (Algorithm A,
+Section 4 of arXiv 1708.00765), not those a particular kernel executes: no
+register moves, control flow, divergence or bookkeeping. The tally additions
+go to the LDS pipe and are not VALU work. With these prices an ideal kernel
+that issued only the algorithm's operations back to back would reach 100%.
 """
 from __future__ import annotations
 
-PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9     # 3.93e13
+PEAK_SLOTS_PER_S = 256 * 128 * 2.4e9        # 7.86e13 (= 157.3 TFLOP/s / 2)
+
+# measured prices (slots per lane-operation)
+F32, I32, F64, TR32 = 1.36, 2.22, 2.41, 4.5
+PHILOX = 88.6
+LOG64, SINCOS64, SQRT64, DIV64 = 188.5, 125.0, 42.2, 28.4
 
 AXES = {"rod": 1, "slab": 1, "ext2d": 2, "cube3d": 3}
 
-STEP = 120 + 17
-SOURCE = 33
-LATERAL = 2
+
+def _price(fp32: bool, f32=0, i32=0, f64=0, tr=0, log=0, sincos=0, sqrt=0, rcp=0):
+    """Slots of an operation mix; `log`, `sincos`, `sqrt`, `rcp` are the
+    precision-dependent calls (FP32 hardware, FP64 library)."""
+    if fp32:
+        return f32 * F32 + i32 * I32 + f64 * F64 + (tr + log + 2 * sincos + sqrt + rcp) * TR32
+    return (f32 * F64 + i32 * I32 + f64 * F64 + tr * TR32 + log * LOG64 + sincos * SINCOS64
+            + sqrt * SQRT64 + rcp * DIV64)
 
 
-def flight_slots(geom: str) -> int:
-    a = AXES[geom]
-    return 3 + 12 + (4 * a + 1) + 4 + (a + 2) + 16 + 3
+def step_slots(fp32: bool) -> float:
+    """Every event step (source or flight): one Philox block, five uniforms."""
+    return PHILOX + _price(fp32, i32=5, f32=5)
 
 
-def scatter_slots(geom: str) -> int:
-    if geom == "ext2d":
-        return 35
-    if geom == "cube3d":
-        return 28
-    return 6          # rod: a sign from one uniform; slab: mu = 2U - 1 and its reciprocal
+def flight_slots(geom: str, fp32: bool, track: bool = True) -> float:
+    lat = AXES[geom] - 1
+    ops = dict(
+        i32=3                              # material selection of 1/Sigma, Lambda, c
+        + 2 + 3 * lat                      # boundary: x face select, per lateral axis compare + 2 selects
+        + 5                                # minimum of three and event code
+        + 1 + 2                            # move: x conversion, boundary snap
+        + 3                                # bin index of the new position
+        + (2 + 1 + 2 + 4 if track else 1)  # track score: ordering, same-bin test, edges, 4 LDS addresses
+        + 3,                               # event dispatch and material switch
+        f32=5                              # distance scalings
+        + 1 + 2 * lat                      # boundary: x scale, per lateral axis subtract + scale
+        + 1 + lat,                         # move: s*ux, lateral FMAs
+        f64=1 + 1 + 1 + (10 if track else 0),   # x distance, x move, bin scale, track partials
+        log=2,
+    )
+    return _price(fp32, **ops)
 
 
-def algorithmic_slots(geom: str, histories: int, flights: int, scatters: int, lateral: int) -> float:
+def scatter_slots(geom: str, fp32: bool) -> float:
+    if geom == "rod":
+        return _price(fp32, i32=2)
+    if geom == "slab":
+        return _price(fp32, f32=2, rcp=1)
+    extra = dict(tr=1, f32=3) if geom == "ext2d" else {}
+    ops = dict(f32=1 + 3 + 2 + extra.get("f32", 0), sincos=1, sqrt=1, rcp=3, tr=extra.get("tr", 0))
+    return _price(fp32, **ops)
+
+
+def source_slots(geom: str, fp32: bool) -> float:
+    base = _price(fp32, i32=2 + 3, f64=1)          # material, bin of the entry point
+    if geom == "rod":
+        return base
+    if geom == "slab":
+        return base + _price(fp32, sqrt=1, rcp=1)
+    return base + scatter_slots(geom, fp32) + _price(fp32, f32=2)   # cosine-law direction + lateral entry
+
+
+def algorithmic_slots(geom: str, histories: int, flights: int, scatters: int, lateral: int,
+                      fp32: bool = True, track: bool = True) -> float:
     """Algorithmic VALU slots of a run from its event counters."""
     steps = histories + flights
-    return (steps * STEP + flights * flight_slots(geom) + scatters * scatter_slots(geom)
-            + histories * SOURCE + lateral * LATERAL)
+    return (steps * step_slots(fp32) + flights * flight_slots(geom, fp32, track)
+            + scatters * scatter_slots(geom, fp32) + histories * source_slots(geom, fp32)
+            + lateral * 2 * F32)
+
+
+def per_unit_table(fp32: bool = True) -> dict:
+    """Slots per unit of work, for the design notes."""
+    return {g: {"step": step_slots(fp32), "flight": flight_slots(g, fp32), "scatter": scatter_slots(g, fp32),
+                "source": source_slots(g, fp32)} for g in AXES}
