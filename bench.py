@@ -58,6 +58,45 @@ def run_batch_steps(cls, torch, probs, specs, steps, warmup, seed_salt):
     return wall, track_ms, tallies
 
 
+def run_served(cls, seconds, rate):
+    """Submit the served workload's Poisson stream in real time; latency is
+    arrival to results on the host, measured by the server's clock."""
+    from paper_1708_00765_amd.inputs import served_requests
+    import numpy as np
+    reqs = served_requests(rate_hz=rate, duration_s=seconds)
+    srv = cls.cls_server_create()
+    live = []
+    t0 = time.perf_counter()
+    try:
+        for t_arr, s in reqs:
+            delay = t0 + t_arr - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            p = make_problem(cls, s, fp32=True)
+            live.append((cls.cls_server_submit(srv, p, s.histories, s.seed), p, s))
+        infos = []
+        for tk, p, s in live:
+            cls.cls_server_wait(srv, tk, 600.0)
+            infos.append(cls.cls_server_request_info(srv, tk))
+        stats = cls.cls_server_get_stats(srv)
+    finally:
+        cls.cls_server_destroy(srv)
+        for _, p, _ in live:
+            cls.cls_destroy_problem(p)
+    lat = np.array([i["done_s"] - i["submit_s"] for i in infos]) * 1e3
+    first = min(i["submit_s"] for i in infos)
+    last = max(i["done_s"] for i in infos)
+    hist = sum(i["histories"] for i in infos)
+    return {"requests": len(reqs), "completed": stats["completed"], "failed": stats["failed"],
+            "offered_rate_hz": rate, "seconds": seconds,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "histories": hist, "histories_per_s": hist / (last - first),
+            "offered_histories_per_s": hist / seconds, "rounds": stats["rounds"],
+            "hbm_peak_bytes": stats["hbm_peak"],
+            "workload": "served: d uniform in {1 (rod, collision flux), 2 (ext2d), 3 (cube3d)}, "
+                        "histories log-uniform in [1e4, 1e8], 10-1000 bins, FP32 tracking"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +108,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=15.0,
+                    help="length of the served Poisson request stream (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -141,6 +183,13 @@ def main() -> int:
         b.copy_(a)
         torch.cuda.synchronize()
 
+    # ---- served: Poisson request stream through the continuous-batching server --
+    served = None
+    if args.serve_seconds > 0:
+        served = run_served(cls, args.serve_seconds, args.serve_rate)
+        log(f"served: {served['completed']} requests, p50 {served['p50_ms']:.1f} ms, "
+            f"p99 {served['p99_ms']:.1f} ms, {served['histories_per_s']:.4g} hist/s")
+
     # ---- CPU oracle on a bounded sample ---------------------------------------
     cpu = None
     if args.cpu_seconds > 0:
@@ -195,6 +244,7 @@ def main() -> int:
                      "frac": achieved / peak, "traffic": None,
                      "kernel_ms": kernel_ms, "algorithmic_slots_per_launch": slots},
         "cpu_baseline": cpu,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -171,16 +171,97 @@ cls_status cls_read_trace(const cls_problem *p, uint64_t *hash, uint32_t *flight
 cls_status cls_run_batch(cls_problem *const *problems, const uint64_t *histories,
                          const uint64_t *seeds, int n);
 
-/* Launch shape used by every run of the calling process (0 keeps the
- * automatic choice): waves per workgroup, workgroups per compute unit, and the
- * largest number of histories per work chunk. */
+/* Graph-captured batch: the same set of problems run repeatedly. The first
+ * cls_batch_run captures reset, tracking, finalize and result copy of one
+ * batched launch in a hipGraph on the batch's own stream; later runs replay it
+ * with new history counts and seeds (launch shape fixed at creation).
+ * Problems must satisfy the cls_run_batch rules, must not use CLS_F_TRACE, and
+ * stay owned by the caller (they must outlive the batch). cls_batch_run is
+ * synchronous; results are read with cls_read_tallies on each problem.
+ * cls_batch_last_ms returns the duration of the last replay (HIP events). */
+typedef struct cls_batch cls_batch;
+cls_status cls_batch_create(cls_problem *const *problems, int n, cls_batch **out);
+cls_status cls_batch_run(cls_batch *b, const uint64_t *histories, const uint64_t *seeds);
+cls_status cls_batch_last_ms(const cls_batch *b, double *ms);
+void cls_batch_destroy(cls_batch *b);
+
+/* Launch shape used by every subsequent run of the process (0 in a field keeps
+ * the automatic choice):
+ *   waves_per_block  1, 2, 4 or 8 waves of 64 lanes per workgroup (automatic: the
+ *                    size that keeps the most waves resident);
+ *   blocks_per_cu    persistent workgroups per compute unit (automatic: as many as
+ *                    are resident at once);
+ *   max_chunk        largest number of histories per work chunk (>= 64; default
+ *                    16384); a chunk is also one batch of the flux error;
+ *   refill_min       idle lanes a wave waits for before it hands out new
+ *                    histories (1..64; default 1: refill every step).
+ * Values out of range give CLS_ERR_INVALID_ARG. */
 typedef struct {
     int waves_per_block;
     int blocks_per_cu;
     int max_chunk;
+    int refill_min;
 } cls_launch_config;
 cls_status cls_set_launch_config(const cls_launch_config *cfg);
 cls_status cls_get_launch_config(cls_launch_config *cfg);
+
+/* Autotuner: time candidate launch shapes (workgroup size, chunk size, refill
+ * threshold) on a calibration sample of about sample_histories histories (0:
+ * 2e7) drawn from `problems` (same rules as cls_run_batch) run as one batched
+ * launch, make the fastest the process-wide launch configuration and return it
+ * in *best (and its rate in histories/s in *best_rate, 0 when it came from the
+ * cache). When the environment variable CLS_AUTOTUNE_CACHE names a file,
+ * results are cached there per device, kernel variant and mesh-size class. */
+cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories, int n,
+                        uint64_t sample_histories, cls_launch_config *best, double *best_rate);
+
+/* Serving: continuous batching of independent requests.
+ *   hbm_budget_bytes     admission limit on the summed device footprint of the
+ *                        admitted requests (0: 80% of the free device memory);
+ *                        a request that does not fit waits in arrival order
+ *                        (one is always admitted when nothing else is);
+ *   round_histories      histories per batched launch ("round"; 0: 3e7);
+ *   max_inflight_rounds  launches queued on the GPU at once (0: 2; at most 8).
+ * A worker thread admits requests, runs rounds of one persistent launch over
+ * the next chunks of every admitted request of one kernel variant, and copies
+ * each request's results back when its last chunk is done. Requests that
+ * arrive while others run join the next round. Each result is the one
+ * cls_run would give for the same problem, histories and seed (integer
+ * tallies bitwise, FP64 sums up to atomic ordering). */
+typedef struct cls_server cls_server;
+typedef struct {
+    size_t hbm_budget_bytes;
+    uint64_t round_histories;
+    int max_inflight_rounds;
+} cls_server_config;
+typedef struct {
+    double submit_s, admit_s, done_s;   /* seconds since server creation (-1: not yet) */
+    uint64_t histories;
+    uint32_t rounds;                     /* launches that carried the request's chunks */
+} cls_request_info;
+typedef struct {
+    uint64_t submitted, completed, failed, pending, active, rounds, histories_completed;
+    size_t hbm_in_use, hbm_peak, hbm_budget;
+    int worker_status;                   /* last worker error (cls_status), 0 if none */
+} cls_server_stats;
+
+/* cfg may be NULL (all defaults). Errors: CLS_ERR_NO_DEVICE, CLS_ERR_DEVICE. */
+cls_status cls_server_create(const cls_server_config *cfg, cls_server **out);
+/* Queue a run of p (not CLS_F_TRACE; one request per problem at a time; the
+ * problem must not be used otherwise until the request is done). */
+cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, uint64_t seed,
+                             uint64_t *ticket);
+/* CLS_OK when done (read results with cls_read_tallies on the problem),
+ * CLS_ERR_NOT_READY while queued or running, or the request's error. */
+cls_status cls_server_poll(cls_server *s, uint64_t ticket);
+/* Block until done or timeout_s seconds (<= 0: no limit) have passed. */
+cls_status cls_server_wait(cls_server *s, uint64_t ticket, double timeout_s);
+cls_status cls_server_request_info(cls_server *s, uint64_t ticket, cls_request_info *info);
+/* Forget a finished request (its ticket becomes unknown). */
+cls_status cls_server_release(cls_server *s, uint64_t ticket);
+cls_status cls_server_get_stats(cls_server *s, cls_server_stats *out);
+/* Finish all submitted work, then stop the worker and free the server. */
+void cls_server_destroy(cls_server *s);
 
 /* Status name and the calling thread's last error detail. */
 const char *cls_status_string(cls_status s);

@@ -48,8 +48,11 @@ EXPORTED = (
     "cls_create_problem", "cls_destroy_problem", "cls_set_stream", "cls_footprint",
     "cls_bind_device_memory", "cls_set_trace_histories", "cls_run", "cls_run_async",
     "cls_query", "cls_synchronize", "cls_read_tallies", "cls_read_trace", "cls_run_batch",
-    "cls_set_launch_config", "cls_get_launch_config", "cls_status_string", "cls_last_error",
-    "cls_version",
+    "cls_batch_create", "cls_batch_run", "cls_batch_last_ms", "cls_batch_destroy",
+    "cls_set_launch_config", "cls_get_launch_config", "cls_autotune",
+    "cls_server_create", "cls_server_submit", "cls_server_poll", "cls_server_wait",
+    "cls_server_request_info", "cls_server_release", "cls_server_get_stats", "cls_server_destroy",
+    "cls_status_string", "cls_last_error", "cls_version",
 )
 
 
@@ -64,7 +67,24 @@ class cls_tallies(ctypes.Structure):
 
 class cls_launch_config(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
-                ("max_chunk", ctypes.c_int)]
+                ("max_chunk", ctypes.c_int), ("refill_min", ctypes.c_int)]
+
+
+class cls_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("round_histories", ctypes.c_uint64),
+                ("max_inflight_rounds", ctypes.c_int)]
+
+
+class cls_request_info(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("histories", ctypes.c_uint64), ("rounds", ctypes.c_uint32)]
+
+
+class cls_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "failed", "pending", "active",
+                                               "rounds", "histories_completed")] + \
+        [(n, ctypes.c_size_t) for n in ("hbm_in_use", "hbm_peak", "hbm_budget")] + \
+        [("worker_status", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -93,6 +113,20 @@ _sig("cls_read_tallies", ctypes.c_int, _P, ctypes.POINTER(cls_tallies), _P, _P, 
 _sig("cls_read_trace", ctypes.c_int, _P, _P, _P, ctypes.c_uint64)
 _sig("cls_run_batch", ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64),
      ctypes.POINTER(ctypes.c_uint64), ctypes.c_int)
+_sig("cls_batch_create", ctypes.c_int, ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P))
+_sig("cls_batch_run", ctypes.c_int, _P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64))
+_sig("cls_batch_last_ms", ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double))
+_sig("cls_batch_destroy", None, _P)
+_sig("cls_autotune", ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint64), ctypes.c_int,
+     ctypes.c_uint64, ctypes.POINTER(cls_launch_config), ctypes.POINTER(ctypes.c_double))
+_sig("cls_server_create", ctypes.c_int, ctypes.POINTER(cls_server_config), ctypes.POINTER(_P))
+_sig("cls_server_submit", ctypes.c_int, _P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64))
+_sig("cls_server_poll", ctypes.c_int, _P, ctypes.c_uint64)
+_sig("cls_server_wait", ctypes.c_int, _P, ctypes.c_uint64, ctypes.c_double)
+_sig("cls_server_request_info", ctypes.c_int, _P, ctypes.c_uint64, ctypes.POINTER(cls_request_info))
+_sig("cls_server_release", ctypes.c_int, _P, ctypes.c_uint64)
+_sig("cls_server_get_stats", ctypes.c_int, _P, ctypes.POINTER(cls_server_stats))
+_sig("cls_server_destroy", None, _P)
 _sig("cls_set_launch_config", ctypes.c_int, ctypes.POINTER(cls_launch_config))
 _sig("cls_get_launch_config", ctypes.c_int, ctypes.POINTER(cls_launch_config))
 _sig("cls_status_string", ctypes.c_char_p, ctypes.c_int)
@@ -197,16 +231,110 @@ def cls_run_batch(problems, histories, seeds, allow_cap: bool = False) -> int:
     return _check(_lib.cls_run_batch(arr, hs, ss, n), "cls_run_batch", allow)
 
 
-def cls_set_launch_config(waves_per_block=0, blocks_per_cu=0, max_chunk=0) -> None:
-    cfg = cls_launch_config(int(waves_per_block), int(blocks_per_cu), int(max_chunk))
+def cls_set_launch_config(waves_per_block=0, blocks_per_cu=0, max_chunk=0, refill_min=0) -> None:
+    cfg = cls_launch_config(int(waves_per_block), int(blocks_per_cu), int(max_chunk), int(refill_min))
     _check(_lib.cls_set_launch_config(ctypes.byref(cfg)), "cls_set_launch_config")
+
+
+def _cfg_dict(cfg) -> dict:
+    return {"waves_per_block": cfg.waves_per_block, "blocks_per_cu": cfg.blocks_per_cu,
+            "max_chunk": cfg.max_chunk, "refill_min": cfg.refill_min}
 
 
 def cls_get_launch_config() -> dict:
     cfg = cls_launch_config()
     _check(_lib.cls_get_launch_config(ctypes.byref(cfg)), "cls_get_launch_config")
-    return {"waves_per_block": cfg.waves_per_block, "blocks_per_cu": cfg.blocks_per_cu,
-            "max_chunk": cfg.max_chunk}
+    return _cfg_dict(cfg)
+
+
+def cls_autotune(problems, histories, sample_histories: int = 0):
+    """Returns (launch config dict, histories/s of the winner or 0.0 from the cache)."""
+    n = len(problems)
+    arr = (_P * n)(*problems)
+    hs = (ctypes.c_uint64 * n)(*[int(v) for v in histories])
+    cfg = cls_launch_config()
+    rate = ctypes.c_double()
+    _check(_lib.cls_autotune(arr, hs, n, int(sample_histories), ctypes.byref(cfg), ctypes.byref(rate)),
+           "cls_autotune")
+    return _cfg_dict(cfg), rate.value
+
+
+# ---- graph-captured batches ---------------------------------------------------
+def cls_batch_create(problems) -> int:
+    n = len(problems)
+    arr = (_P * n)(*problems)
+    h = _P()
+    _check(_lib.cls_batch_create(arr, n, ctypes.byref(h)), "cls_batch_create")
+    return h.value
+
+
+def cls_batch_run(b: int, histories, seeds, allow_cap: bool = False) -> int:
+    n = len(histories)
+    hs = (ctypes.c_uint64 * n)(*[int(v) for v in histories])
+    ss = (ctypes.c_uint64 * n)(*[int(v) & (2**64 - 1) for v in seeds])
+    allow = (CLS_ERR_EVENT_CAP,) if allow_cap else ()
+    return _check(_lib.cls_batch_run(b, hs, ss), "cls_batch_run", allow)
+
+
+def cls_batch_last_ms(b: int) -> float:
+    ms = ctypes.c_double()
+    _check(_lib.cls_batch_last_ms(b, ctypes.byref(ms)), "cls_batch_last_ms")
+    return ms.value
+
+
+def cls_batch_destroy(b: int) -> None:
+    _lib.cls_batch_destroy(b)
+
+
+# ---- serving -----------------------------------------------------------------
+def cls_server_create(hbm_budget_bytes: int = 0, round_histories: int = 0, max_inflight_rounds: int = 0) -> int:
+    cfg = cls_server_config(int(hbm_budget_bytes), int(round_histories), int(max_inflight_rounds))
+    h = _P()
+    _check(_lib.cls_server_create(ctypes.byref(cfg), ctypes.byref(h)), "cls_server_create")
+    return h.value
+
+
+def cls_server_submit(s: int, p: int, histories: int, seed: int) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib.cls_server_submit(s, p, int(histories), int(seed) & (2**64 - 1), ctypes.byref(t)),
+           "cls_server_submit")
+    return t.value
+
+
+def cls_server_poll(s: int, ticket: int) -> bool:
+    st = _lib.cls_server_poll(s, int(ticket))
+    if st == CLS_ERR_NOT_READY:
+        return False
+    _check(st, "cls_server_poll")
+    return True
+
+
+def cls_server_wait(s: int, ticket: int, timeout_s: float = 0.0) -> bool:
+    st = _lib.cls_server_wait(s, int(ticket), float(timeout_s))
+    if st == CLS_ERR_NOT_READY:
+        return False
+    _check(st, "cls_server_wait")
+    return True
+
+
+def cls_server_request_info(s: int, ticket: int) -> dict:
+    info = cls_request_info()
+    _check(_lib.cls_server_request_info(s, int(ticket), ctypes.byref(info)), "cls_server_request_info")
+    return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+def cls_server_release(s: int, ticket: int) -> None:
+    _check(_lib.cls_server_release(s, int(ticket)), "cls_server_release")
+
+
+def cls_server_get_stats(s: int) -> dict:
+    st = cls_server_stats()
+    _check(_lib.cls_server_get_stats(s, ctypes.byref(st)), "cls_server_get_stats")
+    return {k: getattr(st, k) for k, _ in st._fields_}
+
+
+def cls_server_destroy(s: int) -> None:
+    _lib.cls_server_destroy(s)
 
 
 def cls_status_string(status: int) -> str:

@@ -1,0 +1,131 @@
+// Launch-shape autotuner. Candidate shapes -- workgroup size, persistent
+// workgroups per compute unit, histories per chunk and the idle-lane refill
+// threshold ("regroup cadence") -- are timed on a calibration sample of the
+// caller's problems run as one batched launch; the fastest becomes the
+// process-wide launch configuration. Results are cached in a text file (one
+// line per key: device, kernel variant and flux-mesh size class) named by the
+// CLS_AUTOTUNE_CACHE environment variable, when it is set.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cls_runtime.hpp"
+
+using namespace cls;
+using namespace cls::rt;
+
+namespace {
+
+std::string cache_key(const Variant &v, int max_bins)
+{
+    int kc = 64;
+    while (kc < max_bins) kc *= 2;
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "gfx950/g%d/e%d/s%d/%s/k%d", v.geom, v.est, v.src, v.fp32 ? "fp32" : "fp64", kc);
+    return buf;
+}
+
+bool cache_lookup(const std::string &key, cls_launch_config *cfg)
+{
+    const char *path = std::getenv("CLS_AUTOTUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[160];
+        cls_launch_config c;
+        if (std::sscanf(line, "%159s %d %d %d %d", k, &c.waves_per_block, &c.blocks_per_cu, &c.max_chunk,
+                        &c.refill_min) == 5 && key == k) {
+            *cfg = c;       // the last line for a key wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const std::string &key, const cls_launch_config &c)
+{
+    const char *path = std::getenv("CLS_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), c.waves_per_block, c.blocks_per_cu, c.max_chunk, c.refill_min);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories, int n,
+                                   uint64_t sample_histories, cls_launch_config *best, double *best_rate)
+{
+    if (!problems || !histories || n < 1 || !best) return fail(CLS_ERR_INVALID_ARG, "NULL or empty argument");
+    for (int i = 0; i < n; ++i) {
+        if (!problems[i] || histories[i] == 0) return fail(CLS_ERR_INVALID_ARG, "NULL problem or zero histories");
+        if (!same_variant(variant_of(problems[0]), variant_of(problems[i])))
+            return fail(CLS_ERR_INVALID_ARG, "autotune problems must share geometry, source, estimator and precision");
+    }
+    int max_bins = 1;
+    uint64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        max_bins = std::max(max_bins, problems[i]->nbins);
+        total += histories[i];
+    }
+    const std::string key = cache_key(variant_of(problems[0]), max_bins);
+    if (cache_lookup(key, best)) {
+        if (best_rate) *best_rate = 0.0;
+        return cls_set_launch_config(best);
+    }
+    // calibration sample: every problem scaled by the same factor, at least 64 histories
+    if (sample_histories == 0) sample_histories = 20000000ull;
+    const double scale = std::min(1.0, (double)sample_histories / (double)total);
+    std::vector<uint64_t> h(n), seeds(n);
+    uint64_t sample_total = 0;
+    for (int i = 0; i < n; ++i) {
+        h[i] = std::max<uint64_t>(std::min<uint64_t>(64, histories[i]), (uint64_t)(scale * (double)histories[i]));
+        seeds[i] = 0x5DEECE66Dull * (uint64_t)(i + 1);
+        sample_total += h[i];
+    }
+    cls_launch_config saved;
+    cls_status st = cls_get_launch_config(&saved);
+    if (st != CLS_OK) return st;
+    const int waves[] = {0, 2, 4, 8};
+    const int chunks[] = {4096, 16384, 65536};
+    const int refills[] = {1, 4, 16};
+    double best_r = -1.0;
+    cls_launch_config best_c = saved;
+    for (int w : waves)
+        for (int c : chunks)
+            for (int r : refills) {
+                cls_launch_config cfg = {w, 0, c, r};
+                st = cls_set_launch_config(&cfg);
+                if (st != CLS_OK) return st;
+                double ms = 1e30;
+                for (int rep = 0; rep < 2; ++rep) {
+                    st = cls_run_batch(problems, h.data(), seeds.data(), n);
+                    if (st != CLS_OK && st != CLS_ERR_EVENT_CAP) {
+                        (void)cls_set_launch_config(&saved);
+                        return st;
+                    }
+                    cls_tallies t;
+                    (void)cls_read_tallies(problems[0], &t, nullptr, nullptr, 0);
+                    ms = std::min(ms, t.track_ms);
+                }
+                const double rate = (double)sample_total / (ms * 1e-3);
+                if (rate > best_r) {
+                    best_r = rate;
+                    best_c = cfg;
+                }
+            }
+    *best = best_c;
+    if (best_rate) *best_rate = best_r;
+    cache_store(key, best_c);
+    return cls_set_launch_config(&best_c);
+}

@@ -19,54 +19,52 @@
 #include <string>
 #include <vector>
 
-#include "cls.h"
-#include "cls_internal.hpp"
+#include "cls_runtime.hpp"
 
 using namespace cls;
+using namespace cls::rt;
 
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
 
-static cls_status fail(cls_status s, const std::string &msg)
+namespace cls {
+namespace rt {
+
+cls_status fail(cls_status s, const std::string &msg)
 {
     g_last_error = msg;
     return s;
 }
 
-static cls_status hip_fail(hipError_t e, const char *what)
+cls_status hip_fail(hipError_t e, const char *what)
 {
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
     return fail(CLS_ERR_DEVICE, m);
 }
 
-#define HIP_TRY(call)                                              \
-    do {                                                           \
-        hipError_t e_ = (call);                                    \
-        if (e_ != hipSuccess) return hip_fail(e_, #call);          \
-    } while (0)
+}  // namespace rt
+}  // namespace cls
 
 // ---------------------------------------------------------------------------
 // device and launch shape
 // ---------------------------------------------------------------------------
 namespace {
-
-struct DeviceInfo {
-    int id = -1;
-    int cus = 0;
-    size_t lds_per_block = 0;
-};
-
 std::mutex g_mu;
 std::vector<DeviceInfo> g_devices;
-LaunchShape g_shape = {0, 0, 0};
+LaunchShape g_shape = {0, 0, 0, 0};
 
 constexpr int kDefaultWavesPerBlock = 0;   // 0: chosen per kernel (most resident waves)
 constexpr int kDefaultBlocksPerCu = 0;     // 0: as many as fit (occupancy query)
 constexpr int kDefaultMaxChunk = 16384;
 constexpr uint64_t kDefaultMaxSteps = 100000000ull;
 constexpr size_t kLdsLimit = 65536;
+constexpr int kDefaultRefillMin = 1;
+}  // namespace
+
+namespace cls {
+namespace rt {
 
 cls_status device_info(DeviceInfo *out)
 {
@@ -97,52 +95,15 @@ LaunchShape current_shape()
     if (s.waves_per_block <= 0) s.waves_per_block = kDefaultWavesPerBlock;   // may stay 0
     if (s.blocks_per_cu <= 0) s.blocks_per_cu = kDefaultBlocksPerCu;   // may stay 0
     if (s.max_chunk <= 0) s.max_chunk = kDefaultMaxChunk;
+    if (s.refill_min <= 0) s.refill_min = kDefaultRefillMin;
     return s;
 }
 
 size_t align256(size_t v) { return (v + 255u) & ~(size_t)255u; }
 
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// problem object
-// ---------------------------------------------------------------------------
-struct cls_problem {
-    // parameters
-    int d = 0, geom = 0, src = 0, est = 0, nbins = 0;
-    uint32_t flags = 0;
-    double L = 0, sigma[2] = {0, 0}, c[2] = {0, 0}, lam[2] = {0, 0};
-    uint64_t trace_request = 0;
-    // runtime
-    hipStream_t stream = nullptr;
-    int device = -1;
-    char *dev = nullptr;          // workspace base
-    size_t dev_bytes = 0;
-    bool dev_owned = false;
-    size_t trace_cap = 0;         // histories the workspace trace holds
-    // workspace sections
-    DevProblem *d_prob = nullptr;
-    uint64_t *d_items = nullptr;  // [0] = 0, [1] = n_items, [2] = queue head
-    uint64_t *d_counters = nullptr;
-    double *d_sums = nullptr;
-    uint64_t *d_record = nullptr;
-    uint64_t *d_trace_hash = nullptr;
-    uint32_t *d_trace_len = nullptr;
-    // pinned host mirrors
-    DevProblem *h_prob = nullptr;
-    uint64_t *h_items = nullptr;
-    uint64_t *h_record = nullptr;   // counters, then doubles (record_words(K))
-    // run state
-    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
-    bool has_run = false;
-    bool timed_by_events = false;   // track_ms comes from ev_k0/ev_k1
-    float track_ms = 0.0f;
-    uint64_t histories = 0, seed = 0, trace_n = 0;
-};
-
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-static size_t workspace_bytes(int nbins, uint64_t trace_n)
+size_t workspace_bytes(int nbins, uint64_t trace_n)
 {
     size_t b = 0;
     b += align256(sizeof(DevProblem));
@@ -179,7 +140,7 @@ static void release_device(cls_problem *p)
 
 // Make sure the problem has host mirrors, events and a workspace that holds
 // `trace_n` trace entries.
-static cls_status ensure_device(cls_problem *p, uint64_t trace_n)
+cls_status ensure_device(cls_problem *p, uint64_t trace_n)
 {
     DeviceInfo di;
     cls_status st = device_info(&di);
@@ -214,7 +175,7 @@ static cls_status ensure_device(cls_problem *p, uint64_t trace_n)
     return CLS_OK;
 }
 
-static uint64_t chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk)
+uint64_t chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk)
 {
     uint64_t c = (n + 4 * waves_total - 1) / (4 * waves_total);
     c = std::max<uint64_t>(c, 256);
@@ -223,7 +184,7 @@ static uint64_t chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk)
     return std::max<uint64_t>(c, 1);
 }
 
-static void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,
+void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,
                              uint64_t trace_n, DevProblem *out)
 {
     std::memset(out, 0, sizeof *out);
@@ -247,6 +208,7 @@ static void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t 
     out->seed = seed;
     out->histories = histories;
     out->chunk = chunk;
+    out->chunk_base = 0;
     out->trace_n = trace_n;
     out->max_steps = kDefaultMaxSteps;
     out->nbins = p->nbins;
@@ -257,7 +219,17 @@ static void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t 
     out->trace_len = p->d_trace_len;
 }
 
-static Variant variant_of(const cls_problem *p)
+uint64_t trace_count(const cls_problem *p, uint64_t histories)
+{
+    return (p->flags & CLS_F_TRACE) ? std::min(histories, p->trace_request) : 0;
+}
+
+bool same_variant(const Variant &a, const Variant &b)
+{
+    return a.geom == b.geom && a.est == b.est && a.src == b.src && a.fp32 == b.fp32 && a.trace == b.trace;
+}
+
+Variant variant_of(const cls_problem *p)
 {
     Variant v;
     v.geom = p->geom;
@@ -273,8 +245,8 @@ static Variant variant_of(const cls_problem *p)
 // 8 waves) is the one that keeps the most waves resident per compute unit
 // (occupancy query; larger workgroups win ties) and the persistent grid holds
 // as many workgroups as the compute units keep resident at once.
-static cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
-                            size_t *lds, int *lds_stride, LaunchShape *used)
+cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
+                     size_t *lds, int *lds_stride, LaunchShape *used)
 {
     LaunchShape s = current_shape();
     int kp = max_bins + 1;
@@ -313,6 +285,9 @@ static cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di
     *used = s;
     return CLS_OK;
 }
+
+}  // namespace rt
+}  // namespace cls
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -450,10 +425,15 @@ cls_status cls_set_launch_config(const cls_launch_config *cfg)
         cfg->blocks_per_cu > 32 || cfg->max_chunk < 0)
         return fail(CLS_ERR_INVALID_ARG, "launch config out of range");
     if (cfg->max_chunk > 0 && cfg->max_chunk < 64) return fail(CLS_ERR_INVALID_ARG, "max_chunk must be >= 64");
+    if (cfg->refill_min < 0 || cfg->refill_min > 64) return fail(CLS_ERR_INVALID_ARG, "refill_min must lie in [0, 64]");
+    if (cfg->waves_per_block != 0 && cfg->waves_per_block != 1 && cfg->waves_per_block != 2 &&
+        cfg->waves_per_block != 4 && cfg->waves_per_block != 8)
+        return fail(CLS_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
     std::lock_guard<std::mutex> lk(g_mu);
     g_shape.waves_per_block = cfg->waves_per_block;
     g_shape.blocks_per_cu = cfg->blocks_per_cu;
     g_shape.max_chunk = cfg->max_chunk;
+    g_shape.refill_min = cfg->refill_min;
     return CLS_OK;
 }
 
@@ -464,6 +444,7 @@ cls_status cls_get_launch_config(cls_launch_config *cfg)
     cfg->waves_per_block = s.waves_per_block;
     cfg->blocks_per_cu = s.blocks_per_cu;
     cfg->max_chunk = s.max_chunk;
+    cfg->refill_min = s.refill_min;
     return CLS_OK;
 }
 
@@ -471,7 +452,7 @@ cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed)
 {
     if (!p) return fail(CLS_ERR_INVALID_ARG, "problem is NULL");
     if (histories == 0) return fail(CLS_ERR_INVALID_ARG, "histories must be >= 1");
-    const uint64_t trace_n = (p->flags & CLS_F_TRACE) ? std::min(histories, p->trace_request) : 0;
+    const uint64_t trace_n = trace_count(p, histories);
     cls_status st = ensure_device(p, trace_n);
     if (st != CLS_OK) return st;
     if (trace_n > p->trace_cap) return fail(CLS_ERR_INVALID_ARG, "bound device memory too small for the trace");
@@ -503,6 +484,7 @@ cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed)
     a.queue_head = p->d_items + 2;
     a.nprobs = 1;
     a.lds_stride = stride;
+    a.refill_min = used.refill_min;
     HIP_TRY(hipEventRecord(p->ev_k0, s));
     HIP_TRY(launch_track(variant_of(p), a, grid, block, lds, s));
     HIP_TRY(hipEventRecord(p->ev_k1, s));
@@ -657,8 +639,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     for (int i = 0; i < n; ++i) {
         if (!problems[i]) return fail(CLS_ERR_INVALID_ARG, "NULL problem in batch");
         if (histories[i] == 0) return fail(CLS_ERR_INVALID_ARG, "histories must be >= 1");
-        const Variant a = variant_of(problems[0]), b = variant_of(problems[i]);
-        if (a.geom != b.geom || a.est != b.est || a.src != b.src || a.fp32 != b.fp32 || a.trace != b.trace)
+        if (!same_variant(variant_of(problems[0]), variant_of(problems[i])))
             return fail(CLS_ERR_INVALID_ARG, "batch problems must share geometry, source, estimator and precision");
         for (int j = 0; j < i; ++j)
             if (problems[j] == problems[i]) return fail(CLS_ERR_INVALID_ARG, "a problem appears twice in the batch");
@@ -668,7 +649,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     size_t rec_words = 0;
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
-        const uint64_t tn = (p->flags & CLS_F_TRACE) ? std::min(histories[i], p->trace_request) : 0;
+        const uint64_t tn = trace_count(p, histories[i]);
         cls_status st = ensure_device(p, tn);
         if (st != CLS_OK) return st;
         if (tn > p->trace_cap) return fail(CLS_ERR_INVALID_ARG, "bound device memory too small for the trace");
@@ -701,7 +682,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
-        const uint64_t tn = (p->flags & CLS_F_TRACE) ? std::min(histories[i], p->trace_request) : 0;
+        const uint64_t tn = trace_count(p, histories[i]);
         const uint64_t chunk = chunk_size(histories[i], waves_total, (uint64_t)used.max_chunk);
         fill_dev_problem(p, histories[i], seeds[i], chunk, tn, &h_probs[i]);
         h_probs[i].record = d_rec + off;
@@ -718,6 +699,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     a.queue_head = d_items + n + 1;
     a.nprobs = n;
     a.lds_stride = stride;
+    a.refill_min = used.refill_min;
     HIP_TRY(hipEventRecord(bs->k0, s));
     HIP_TRY(launch_track(variant_of(problems[0]), a, grid, block, lds, s));
     HIP_TRY(hipEventRecord(bs->k1, s));

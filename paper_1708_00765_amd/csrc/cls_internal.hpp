@@ -50,6 +50,7 @@ struct alignas(16) DevProblem {
     uint64_t seed;
     uint64_t histories;
     uint64_t chunk;             // histories per work item (batch)
+    uint64_t chunk_base;        // chunk index of this launch's first work item of the problem
     uint64_t trace_n;           // histories with a recorded trace
     uint64_t max_steps;         // flight cap per history
     int32_t nbins;
@@ -68,6 +69,7 @@ struct TrackArgs {
     uint64_t *queue_head;        // work-item counter (zeroed before the launch)
     int nprobs;
     int lds_stride;              // doubles per tally buffer (>= max nbins + 1, even)
+    int refill_min;              // idle lanes a wave waits for before handing out histories
 };
 
 // LDS per wave beyond its two tally buffers: score sums of the two slots
@@ -79,6 +81,7 @@ struct LaunchShape {
     int waves_per_block;
     int blocks_per_cu;
     int max_chunk;
+    int refill_min;
 };
 
 // Kernel variants: geometry x estimator x source x precision x trace.

@@ -1,0 +1,84 @@
+// Private host runtime of the CLS library: the problem object behind the
+// opaque C handle and the helpers that the problem, batch, graph, autotuning
+// and serving entry points share. Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string>
+
+#include "cls.h"
+#include "cls_internal.hpp"
+
+// ---------------------------------------------------------------------------
+// problem object
+// ---------------------------------------------------------------------------
+struct cls_problem {
+    // parameters
+    int d = 0, geom = 0, src = 0, est = 0, nbins = 0;
+    uint32_t flags = 0;
+    double L = 0, sigma[2] = {0, 0}, c[2] = {0, 0}, lam[2] = {0, 0};
+    uint64_t trace_request = 0;
+    // runtime
+    hipStream_t stream = nullptr;
+    int device = -1;
+    char *dev = nullptr;          // workspace base
+    size_t dev_bytes = 0;
+    bool dev_owned = false;
+    size_t trace_cap = 0;         // histories the workspace trace holds
+    // workspace sections
+    cls::DevProblem *d_prob = nullptr;
+    uint64_t *d_items = nullptr;  // [0] = 0, [1] = n_items, [2] = queue head
+    uint64_t *d_counters = nullptr;
+    double *d_sums = nullptr;
+    uint64_t *d_record = nullptr;
+    uint64_t *d_trace_hash = nullptr;
+    uint32_t *d_trace_len = nullptr;
+    // pinned host mirrors
+    cls::DevProblem *h_prob = nullptr;
+    uint64_t *h_items = nullptr;
+    uint64_t *h_record = nullptr;   // counters, then doubles (record_words(K))
+    // run state
+    hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
+    bool has_run = false;
+    bool timed_by_events = false;   // track_ms comes from ev_k0/ev_k1
+    float track_ms = 0.0f;
+    uint64_t histories = 0, seed = 0, trace_n = 0;
+};
+
+
+namespace cls {
+namespace rt {
+
+cls_status fail(cls_status s, const std::string &msg);
+cls_status hip_fail(hipError_t e, const char *what);
+
+#define HIP_TRY(call)                                                   \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) return ::cls::rt::hip_fail(e_, #call);    \
+    } while (0)
+
+struct DeviceInfo {
+    int id = -1;
+    int cus = 0;
+    size_t lds_per_block = 0;
+};
+
+cls_status device_info(DeviceInfo *out);
+LaunchShape current_shape();
+size_t align256(size_t v);
+size_t workspace_bytes(int nbins, uint64_t trace_n);
+cls_status ensure_device(cls_problem *p, uint64_t trace_n);
+uint64_t trace_count(const cls_problem *p, uint64_t histories);
+uint64_t chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk);
+void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,
+                      uint64_t trace_n, DevProblem *out);
+Variant variant_of(const cls_problem *p);
+bool same_variant(const Variant &a, const Variant &b);
+cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
+                     size_t *lds, int *lds_stride, LaunchShape *used);
+
+}  // namespace rt
+}  // namespace cls

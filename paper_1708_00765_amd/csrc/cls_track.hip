@@ -406,7 +406,10 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
 
     for (;;) {
         // ---------------- hand out histories to idle lanes ----------------
+        // Idle lanes are refilled once at least refill_min of them wait (or the
+        // whole wave is idle): fewer, fuller source steps against idle lanes.
         uint64_t dead = ballot(!L.alive);
+        if (dead != ~0ull && popc(dead) < (uint32_t)A.refill_min) dead = 0;
         while (dead != 0) {
             if (!s_open[cur] || s_next[cur] == s_cnt[cur]) {
                 const int o = cur ^ 1;
@@ -424,7 +427,7 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                     if (A.item_start[mid] <= item) lo = mid; else hi = mid;
                 }
                 const DevProblem &P = A.probs[lo];
-                const uint64_t first = (item - A.item_start[lo]) * P.chunk;
+                const uint64_t first = (P.chunk_base + item - A.item_start[lo]) * P.chunk;
                 const uint64_t rest = P.histories - first;
                 s_h0[o] = first;
                 s_cnt[o] = (uint32_t)(rest < P.chunk ? rest : P.chunk);

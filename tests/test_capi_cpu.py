@@ -26,7 +26,7 @@ def cls():
 
 def test_every_declared_function_is_exported(cls):
     names = declared_functions()
-    assert len(names) >= 18
+    assert len(names) >= 31
     for n in names:
         assert hasattr(cls._lib, n), n
     assert set(names) == set(cls.EXPORTED)
@@ -92,10 +92,37 @@ def test_launch_config_validation(cls):
         cls.cls_set_launch_config(waves_per_block=9)
     with pytest.raises(cls.ClsError):
         cls.cls_set_launch_config(max_chunk=10)
-    cls.cls_set_launch_config(2, 4, 1024)
-    assert cls.cls_get_launch_config() == {"waves_per_block": 2, "blocks_per_cu": 4, "max_chunk": 1024}
-    cls.cls_set_launch_config(0, 0, 0)
+    with pytest.raises(cls.ClsError):
+        cls.cls_set_launch_config(waves_per_block=3)
+    with pytest.raises(cls.ClsError):
+        cls.cls_set_launch_config(refill_min=65)
+    cls.cls_set_launch_config(2, 4, 1024, 8)
+    assert cls.cls_get_launch_config() == {"waves_per_block": 2, "blocks_per_cu": 4, "max_chunk": 1024,
+                                           "refill_min": 8}
+    cls.cls_set_launch_config(0, 0, 0, 0)
     assert cls.cls_get_launch_config() == old
+
+
+def test_server_and_graph_need_a_device(cls):
+    # without a GPU the server and graph batches fail cleanly with a status code
+    with pytest.raises(cls.ClsError) as ei:
+        cls.cls_server_create()
+    assert ei.value.status == cls.CLS_ERR_NO_DEVICE
+    p = cls.cls_create_problem(3, 10.0, (0.5, 1.0), (0.2, 0.9), (1.0, 0.3))
+    try:
+        with pytest.raises(cls.ClsError) as ei:
+            cls.cls_batch_create([p])
+        assert ei.value.status == cls.CLS_ERR_NO_DEVICE
+        t = cls.cls_create_problem(3, 10.0, (0.5, 1.0), (0.2, 0.9), (1.0, 0.3), flags=cls.CLS_F_TRACE)
+        with pytest.raises(cls.ClsError) as ei:      # traces are not recorded by graph batches
+            cls.cls_batch_create([t])
+        assert ei.value.status == cls.CLS_ERR_INVALID_ARG
+        cls.cls_destroy_problem(t)
+        with pytest.raises(cls.ClsError) as ei:
+            cls.cls_autotune([p], [0])
+        assert ei.value.status == cls.CLS_ERR_INVALID_ARG
+    finally:
+        cls.cls_destroy_problem(p)
 
 
 def test_batch_argument_validation(cls):
