@@ -58,6 +58,42 @@ def run_batch_steps(cls, torch, probs, specs, steps, warmup, seed_salt):
     return wall, track_ms, tallies
 
 
+def run_ext2d_comparison(cls, torch, stream, steps):
+    """The 256 uneven ext2d sets (1e4..1e7 histories, 100..1000 bins): one batched
+    FP32 persistent launch per pass vs one plain FP64 launch per set."""
+    from paper_1708_00765_amd.inputs import workload
+    specs = workload("ext2d_batched")
+    total = sum(s.histories for s in specs)
+    hist = [s.histories for s in specs]
+    p32 = [make_problem(cls, s, fp32=True) for s in specs]
+    p64 = [make_problem(cls, s, fp32=False) for s in specs]
+    try:
+        for p in p32 + p64:
+            cls.cls_set_stream(p, stream)
+        cls.cls_run_batch(p32, hist, [s.seed for s in specs])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            cls.cls_run_batch(p32, hist, [s.seed + k + 1 for s in specs])
+        torch.cuda.synchronize()
+        w32 = (time.perf_counter() - t0) / steps
+        for p, s in zip(p64[:8], specs[:8]):
+            cls.cls_run(p, min(s.histories, 10000), s.seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            for p, s in zip(p64, specs):
+                cls.cls_run(p, s.histories, s.seed + k + 1)
+        torch.cuda.synchronize()
+        w64 = (time.perf_counter() - t0) / steps
+    finally:
+        for p in p32 + p64:
+            cls.cls_destroy_problem(p)
+    return {"sets": len(specs), "histories": total, "fp32_batched_value": total / w32,
+            "fp64_plain_value": total / w64, "ratio": w64 / w32, "fp32_batched_ms": 1e3 * w32,
+            "fp64_plain_ms": 1e3 * w64, "unit": "histories/s"}
+
+
 def run_served(cls, seconds, rate):
     """Submit the served workload's Poisson stream in real time; latency is
     arrival to results on the host, measured by the server's clock."""
@@ -111,6 +147,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="length of the served Poisson request stream (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
+    ap.add_argument("--ext2d-steps", type=int, default=2,
+                    help="timed passes of the 256-set ext2d comparison (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -183,6 +221,13 @@ def main() -> int:
         b.copy_(a)
         torch.cuda.synchronize()
 
+    # ---- 256 uneven ext2d sets: one batched FP32 launch vs one FP64 launch per set --
+    ext2d = None
+    if args.ext2d_steps > 0:
+        ext2d = run_ext2d_comparison(cls, torch, stream, args.ext2d_steps)
+        log(f"ext2d 256 sets: fp32 batched {ext2d['fp32_batched_value']:.4g} hist/s, fp64 plain "
+            f"{ext2d['fp64_plain_value']:.4g} hist/s, ratio {ext2d['ratio']:.2f}")
+
     # ---- served: Poisson request stream through the continuous-batching server --
     served = None
     if args.serve_seconds > 0:
@@ -245,6 +290,7 @@ def main() -> int:
                      "kernel_ms": kernel_ms, "algorithmic_slots_per_launch": slots},
         "cpu_baseline": cpu,
         "served": served,
+        "ext2d_batched_vs_fp64_plain": ext2d,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -133,8 +133,13 @@ struct Prm {
     uint32_t *trace_len;
 };
 
+// The problem records are written by the host before the launch and only read
+// by the kernel: reading them through the constant address space lets the
+// compiler use scalar loads (SGPRs) for a wave-uniform record.
+typedef const __attribute__((address_space(4))) DevProblem ConstProblem;
+
 template <typename R>
-__device__ __forceinline__ Prm<R> load_prm(const DevProblem &P)
+__device__ __forceinline__ Prm<R> load_prm(ConstProblem &P)
 {
     Prm<R> q;
     if constexpr (std::is_same<R, float>::value) {
@@ -426,7 +431,7 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                     const int mid = (lo + hi) >> 1;
                     if (A.item_start[mid] <= item) lo = mid; else hi = mid;
                 }
-                const DevProblem &P = A.probs[lo];
+                ConstProblem &P = ((ConstProblem *)A.probs)[lo];
                 const uint64_t first = (P.chunk_base + item - A.item_start[lo]) * P.chunk;
                 const uint64_t rest = P.histories - first;
                 s_h0[o] = first;
@@ -470,7 +475,8 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             const int pidc = __shfl(L.pid, first, 64);
             const bool mine = L.alive && L.pid == pidc && ((todo >> lane) & 1ull);
             if (mine) {
-                const Prm<R> P = load_prm<R>(A.probs[__builtin_amdgcn_readfirstlane(pidc)]);
+                ConstProblem *cp = (ConstProblem *)A.probs;
+                const Prm<R> P = load_prm<R>(cp[__builtin_amdgcn_readfirstlane(pidc)]);
                 ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + L.slot * KP);
             }
             todo &= ~ballot(mine);
@@ -511,7 +517,7 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 if (s_open[s] && s_next[s] == s_cnt[s] && s_live[s] == 0) {
-                    const DevProblem &P = A.probs[s_pid[s]];
+                    ConstProblem &P = ((ConstProblem *)A.probs)[s_pid[s]];
                     const int KK = P.nbins;
                     double *b = wbuf + s * KP;
                     double *Sk = P.sums + 2;
