@@ -198,6 +198,7 @@ void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, u
     }
     out->p0 = p->lam[0] / (p->lam[0] + p->lam[1]);
     out->Lf = (float)p->L;
+    out->dxf = (float)out->dx;
     out->p0f = (float)out->p0;
     for (int i = 0; i < 2; ++i) {
         out->isig[i] = 1.0 / p->sigma[i];

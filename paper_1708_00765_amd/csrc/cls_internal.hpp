@@ -54,7 +54,7 @@ struct alignas(16) DevProblem {
     uint64_t trace_n;           // histories with a recorded trace
     uint64_t max_steps;         // flight cap per history
     int32_t nbins;
-    int32_t pad0;
+    float dxf;                  // FP32 copy of dx
     uint64_t *counters;         // C_COUNT u64
     double *sums;               // [0] score sum, [1] score square sum, [2..2+K) S_k, [2+K..2+2K) Q_k
     uint64_t *record;           // finalize output, record_words(K) words

@@ -49,6 +49,8 @@ struct Math<float> {
     static __device__ __forceinline__ float sqrt_(float v) { return __builtin_amdgcn_sqrtf(v); }
     static __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
     static __device__ __forceinline__ float rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
+    static __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    static __device__ __forceinline__ float abs_(float v) { return __builtin_fabsf(v); }
     // sin and cos of 2 pi u: the hardware takes its argument in turns
     static __device__ __forceinline__ void sincos_turns(float u, float *s, float *c)
     {
@@ -63,6 +65,8 @@ struct Math<double> {
     static __device__ __forceinline__ double sqrt_(double v) { return sqrt(v); }
     static __device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
     static __device__ __forceinline__ double rsqrt(double v) { return 1.0 / sqrt(v); }
+    static __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+    static __device__ __forceinline__ double abs_(double v) { return __builtin_fabs(v); }
     static __device__ __forceinline__ void sincos_turns(double u, double *s, double *c)
     {
         sincos(6.283185307179586476925286766559 * u, s, c);
@@ -124,7 +128,7 @@ static_assert(S_NCTR <= kSlotCounters, "slot counters do not fit their LDS area"
 // lane otherwise (a wave straddling two work chunks of different problems).
 template <typename R>
 struct Prm {
-    R isig0, isig1, c0, c1, lam0, lam1, p0, Lr;
+    R isig0, isig1, c0, c1, lam0, lam1, p0, Lr, dxr;
     double Ld, inv_dx, dx;
     int K;
     uint32_t key_lo, key_hi;
@@ -146,12 +150,12 @@ __device__ __forceinline__ Prm<R> load_prm(ConstProblem &P)
         q.isig0 = P.isigf[0]; q.isig1 = P.isigf[1];
         q.c0 = P.cf[0]; q.c1 = P.cf[1];
         q.lam0 = P.lamf[0]; q.lam1 = P.lamf[1];
-        q.p0 = P.p0f; q.Lr = P.Lf;
+        q.p0 = P.p0f; q.Lr = P.Lf; q.dxr = P.dxf;
     } else {
         q.isig0 = P.isig[0]; q.isig1 = P.isig[1];
         q.c0 = P.c[0]; q.c1 = P.c[1];
         q.lam0 = P.lam[0]; q.lam1 = P.lam[1];
-        q.p0 = P.p0; q.Lr = P.L;
+        q.p0 = P.p0; q.Lr = P.L; q.dxr = P.dx;
     }
     q.Ld = P.L; q.inv_dx = P.inv_dx; q.dx = P.dx; q.K = P.nbins;
     q.key_lo = (uint32_t)P.seed; q.key_hi = (uint32_t)(P.seed >> 32);
@@ -160,12 +164,19 @@ __device__ __forceinline__ Prm<R> load_prm(ConstProblem &P)
     return q;
 }
 
-// Per-lane particle state.
+// Per-lane particle state. The lateral coordinates are kept as the distance
+// along each axis to the lateral face the particle is heading for (the face
+// at y = L when u_y > 0, at y = 0 otherwise), which is all that the flight
+// needs: the distance to that face is dy / |u_y|, a flight of length s takes
+// s |u_y| off it, a mirror reflection resets it to L, and a new direction
+// whose u_y has the other sign turns it into L - dy.
 template <typename R>
 struct Lane {
     double x;
-    R y, z, ux, uy, uz;
-    R iux, iuy, iuz, ig;     // cached 1/u components and 1/(chord factor)
+    R dy, dz;                // distance along y / z to the face headed for
+    R ux, uy, uz;
+    R iux, aiuy, aiuz, ig;   // 1/u_x, |1/u_y|, |1/u_z|, 1/(chord factor)
+    R fx;                    // x inside its flux bin, in bin widths (FP32 track-length)
     double tscore;           // this history's flux score
     uint64_t h;
     uint64_t hash;
@@ -175,11 +186,16 @@ struct Lane {
     bool alive;
 };
 
-__device__ __forceinline__ int bin_index(double x, double inv_dx, int K)
+// Flux bin of x (truncation equals floor for x >= 0; positions rounded just
+// outside [0, L] map to the end bins) and, in FP32, the position of x inside
+// that bin in bin widths.
+template <typename R>
+__device__ __forceinline__ int bin_of(double x, double inv_dx, int K, R *frac)
 {
-    // truncation equals floor for x >= 0; slightly negative x maps to bin 0
-    const int k = (int)(x * inv_dx);
-    return k < K - 1 ? (k > 0 ? k : 0) : K - 1;
+    const double t = x * inv_dx;
+    const int k = min(max((int)t, 0), K - 1);
+    if (sizeof(R) == 4) *frac = (R)(t - (double)k);
+    return k;
 }
 
 // One event step of one lane: the source (step 0) or a flight. Returns the
@@ -190,7 +206,6 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
     using MM = Math<R>;
     constexpr int AXES = (G == GEOM_EXT2D) ? 2 : (G == GEOM_CUBE3D ? 3 : 1);
     constexpr bool DIR3 = (G == GEOM_EXT2D || G == GEOM_CUBE3D);
-    const R INF = (R)__builtin_huge_val();
 
     const Block5 B = philox_u23(L.step, 0u, L.h, P.key_lo, P.key_hi);
     int ev;
@@ -198,8 +213,12 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
     R cos_t = 0, turns = 0;
     if (L.step == 0) {
         // ---- source (Section 2; Sec. 4.1-4.3) ----
+        // Lateral coordinates go into dy / dz with u_y = u_z = -1 standing for
+        // "heading for the face at 0"; the direction sampler below converts
+        // them to distances to the faces the sampled direction heads for.
         L.m = (unit<R>(B.k[0]) < P.p0) ? 0 : 1;
-        L.x = 0.0; L.y = 0; L.z = 0;
+        L.x = 0.0; L.dy = 0; L.dz = 0;
+        L.uy = (R)-1; L.uz = (R)-1;
         if (SRC == SRC_FACE) {
             if (G == GEOM_ROD) {
                 L.ux = 1; L.iux = 1;
@@ -211,8 +230,8 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
                 need_dir = true; src_dir = true;
                 cos_t = MM::sqrt_(unit<R>(B.k[1]));
                 turns = unit<R>(B.k[2]);
-                L.y = P.Lr * unit<R>(B.k[3]);
-                if (G == GEOM_CUBE3D) L.z = P.Lr * unit<R>(B.k[4]);
+                L.dy = P.Lr * unit<R>(B.k[3]);
+                if (G == GEOM_CUBE3D) L.dz = P.Lr * unit<R>(B.k[4]);
             }
         } else {
             L.x = P.Ld * (double)unit<R>(B.k[1]);
@@ -222,9 +241,9 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
             } else if (G == GEOM_SLAB) {
                 L.ux = (R)2 * unit<R>(B.k[2]) - (R)1;
                 L.iux = MM::rcp(L.ux);
-                L.ig = L.iux < 0 ? -L.iux : L.iux;
+                L.ig = MM::abs_(L.iux);
             } else if (G == GEOM_EXT2D) {
-                L.y = P.Lr * unit<R>(B.k[2]);
+                L.dy = P.Lr * unit<R>(B.k[2]);
                 need_dir = true;
                 cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
                 turns = unit<R>(B.k[4]);
@@ -232,12 +251,12 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
                 need_dir = true;
                 cos_t = (R)2 * unit<R>(B.k[2]) - (R)1;
                 turns = unit<R>(B.k[3]);
-                L.y = P.Lr * unit<R>(B.k[4]);
+                L.dy = P.Lr * unit<R>(B.k[4]);
                 const Block5 B2 = philox_u23(0u, 1u, L.h, P.key_lo, P.key_hi);
-                L.z = P.Lr * unit<R>(B2.k[0]);
+                L.dz = P.Lr * unit<R>(B2.k[0]);
             }
         }
-        L.kcur = bin_index(L.x, P.inv_dx, P.K);
+        L.kcur = bin_of<R>(L.x, P.inv_dx, P.K, &L.fx);
         ev = EV_SOURCE;
         if (TRACE) L.hash = fnv_event(L.hash, EV_SOURCE, L.m, L.kcur);
     } else if ((uint64_t)L.step > P.max_steps) {
@@ -250,77 +269,85 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         const R lam_m = mf ? P.lam1 : P.lam0;
         const R lc = MM::neglog(unit<R>(B.k[0])) * isig_m;
         const R li = MM::neglog(unit<R>(B.k[1])) * lam_m * L.ig;
-        R lb;
-        int face;
-        {
-            const double dxf = L.ux > 0 ? (P.Ld - L.x) : (0.0 - L.x);
-            lb = (L.ux == 0) ? INF : (R)dxf * L.iux;
-            face = L.ux > 0 ? 1 : 0;
-        }
+        // distance to the box: |distance to the face headed for| / |u| per
+        // axis; a direction parallel to an axis gives +inf (or NaN for a
+        // particle on that face), which never wins
+        const double xh = L.ux > 0 ? P.Ld - L.x : L.x;
+        R lb = (R)xh * MM::abs_(L.iux);
+        int ax = 0;
         if (AXES >= 2) {
-            const R d = L.uy > 0 ? (P.Lr - L.y) : (R)0 - L.y;
-            const R l = (L.uy == 0) ? INF : d * L.iuy;
-            if (l < lb) { lb = l; face = L.uy > 0 ? 3 : 2; }
+            const R l = L.dy * L.aiuy;
+            if (l < lb) { lb = l; ax = 1; }
         }
         if (AXES >= 3) {
-            const R d = L.uz > 0 ? (P.Lr - L.z) : (R)0 - L.z;
-            const R l = (L.uz == 0) ? INF : d * L.iuz;
-            if (l < lb) { lb = l; face = L.uz > 0 ? 5 : 4; }
+            const R l = L.dz * L.aiuz;
+            if (l < lb) { lb = l; ax = 2; }
         }
         const bool bnd = (lb <= lc) && (lb <= li);
         const bool coll = !bnd && (lc <= li);
         R s = bnd ? lb : (coll ? lc : li);
-        if (FP32) s = s > (R)0 ? s : (R)0;      // l_b <= 0: cross at once
+        if (FP32) s = s > (R)0 ? s : (R)0;      // a face already passed by rounding: cross at once
         const double xa = L.x;
         const int ka0 = L.kcur;
+        const R fa = L.fx;
         L.x += (double)(s * L.ux);
-        if (AXES >= 2) L.y += s * L.uy;
-        if (AXES >= 3) L.z += s * L.uz;
-        if (bnd) {
-            const R fv = (face & 1) ? P.Lr : (R)0;
-            if (face < 2) L.x = (face & 1) ? P.Ld : 0.0;
-            else if (face < 4) L.y = fv;
-            else L.z = fv;
-        }
-        if (FP32) {
-            L.x = L.x < 0.0 ? 0.0 : (L.x > P.Ld ? P.Ld : L.x);
-            if (AXES >= 2) L.y = L.y < (R)0 ? (R)0 : (L.y > P.Lr ? P.Lr : L.y);
-            if (AXES >= 3) L.z = L.z < (R)0 ? (R)0 : (L.z > P.Lr ? P.Lr : L.z);
-        }
-        L.kcur = bin_index(L.x, P.inv_dx, P.K);
+        if (AXES >= 2) L.dy = MM::fma_(-s, MM::abs_(L.uy), L.dy);
+        if (AXES >= 3) L.dz = MM::fma_(-s, MM::abs_(L.uz), L.dz);
+        if (bnd && ax == 0) L.x = L.ux > 0 ? P.Ld : 0.0;
+        // A lateral coordinate rounded past its face is harmless: the next
+        // distance to that face is <= 0, so the particle reaches it at once.
+        L.kcur = bin_of<R>(L.x, P.inv_dx, P.K, &L.fx);
         // ---- track-length score in difference form ----
+        // A flight from bin ka up to bin kb adds its partial overlap pa to ka,
+        // the full width to every bin strictly between and its partial
+        // overlap pb to kb: in difference form D[ka] += pa, D[ka+1] += full -
+        // pa, D[kb] += pb - full, D[kb+1] -= pb. A flight inside one bin is the
+        // same update with pa = s and full = pb = 0, so every flight issues
+        // the same four adds.
         if (EST == EST_TRACK) {
             const double sd = (double)s;
-            if (sd > 0.0) {
-                L.tscore += sd;
-                const bool up = L.x >= xa;
-                const int ka = up ? ka0 : L.kcur;
-                const int kb = up ? L.kcur : ka0;
-                if (ka == kb) {
-                    lds_add(tal + ka, sd);
-                    lds_add(tal + ka + 1, -sd);
-                } else {
-                    const double lo = up ? xa : L.x;
-                    const double hi = up ? L.x : xa;
-                    const double w = (double)(L.iux < 0 ? -L.iux : L.iux);
-                    const double pa = ((double)(ka + 1) * P.dx - lo) * w;
-                    const double pb = (hi - (double)kb * P.dx) * w;
-                    const double full = P.dx * w;
-                    lds_add(tal + ka, pa);
-                    lds_add(tal + ka + 1, full - pa);
-                    lds_add(tal + kb, pb - full);
-                    lds_add(tal + kb + 1, -pb);
-                }
+            L.tscore += sd;
+            const bool up = L.x >= xa;
+            const int ka = up ? ka0 : L.kcur;
+            const int kb = up ? L.kcur : ka0;
+            const bool one = (ka == kb);
+            if (FP32) {
+                // overlaps from the in-bin positions: (1 - f) of the lower
+                // end's bin and f of the upper end's, times the bin width
+                // along the track
+                const R dxw = P.dxr * MM::abs_(L.iux);
+                const R pa = one ? s : ((R)1 - (up ? fa : L.fx)) * dxw;
+                const R pb = one ? (R)0 : (up ? L.fx : fa) * dxw;
+                const R full = one ? (R)0 : dxw;
+                lds_add(tal + ka, (double)pa);
+                lds_add(tal + ka + 1, (double)(full - pa));
+                lds_add(tal + kb, (double)(pb - full));
+                lds_add(tal + kb + 1, -(double)pb);
+            } else {
+                const double lo = up ? xa : L.x;
+                const double hi = up ? L.x : xa;
+                const double w = (double)MM::abs_(L.iux);
+                const double pa = one ? sd : ((double)(ka + 1) * P.dx - lo) * w;
+                const double pb = one ? 0.0 : (hi - (double)kb * P.dx) * w;
+                const double full = one ? 0.0 : P.dx * w;
+                lds_add(tal + ka, pa);
+                lds_add(tal + ka + 1, full - pa);
+                lds_add(tal + kb, pb - full);
+                lds_add(tal + kb + 1, -pb);
             }
         }
         // ---- the event ----
         if (bnd) {
-            if (face == 0) ev = EV_LEAK_XLO;
-            else if (face == 1) ev = EV_LEAK_XHI;
-            else {
-                ev = EV_REFL_YLO + (face - 2);
-                if (face < 4) { L.uy = -L.uy; L.iuy = -L.iuy; }
-                else { L.uz = -L.uz; L.iuz = -L.iuz; }
+            if (ax == 0) {
+                ev = L.ux > 0 ? EV_LEAK_XHI : EV_LEAK_XLO;
+            } else if (AXES >= 2 && ax == 1) {
+                ev = L.uy > 0 ? EV_REFL_YHI : EV_REFL_YLO;
+                L.uy = -L.uy;
+                L.dy = P.Lr;
+            } else {
+                ev = L.uz > 0 ? EV_REFL_ZHI : EV_REFL_ZLO;
+                L.uz = -L.uz;
+                L.dz = P.Lr;
             }
         } else if (!coll) {
             ev = EV_INTERFACE;
@@ -339,7 +366,7 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
                 } else if (G == GEOM_SLAB) {
                     L.ux = (R)2 * unit<R>(B.k[3]) - (R)1;
                     L.iux = MM::rcp(L.ux);
-                    L.ig = L.iux < 0 ? -L.iux : L.iux;
+                    L.ig = MM::abs_(L.iux);
                 } else {
                     need_dir = true;
                     cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
@@ -363,12 +390,19 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         if (FP32) st = MM::sqrt_(((R)1 - cos_t) * ((R)1 + cos_t));
         else st = MM::sqrt_((R)1 - cos_t * cos_t);
         const R a = st * cs, b = st * sn;
-        if (src_dir) { L.ux = cos_t; L.uy = a; L.uz = b; }
-        else { L.ux = a; L.uy = b; L.uz = cos_t; }
-        L.iux = MM::rcp(L.ux);
-        L.iuy = MM::rcp(L.uy);
-        L.iuz = MM::rcp(L.uz);
-        if (G == GEOM_EXT2D) L.ig = MM::rsqrt(L.ux * L.ux + L.uy * L.uy);
+        R nx, ny, nz;
+        if (src_dir) { nx = cos_t; ny = a; nz = b; }
+        else { nx = a; ny = b; nz = cos_t; }
+        if ((ny > 0) != (L.uy > 0)) L.dy = P.Lr - L.dy;
+        L.ux = nx; L.uy = ny;
+        L.iux = MM::rcp(nx);
+        L.aiuy = MM::rcp(MM::abs_(ny));
+        if (G == GEOM_CUBE3D) {
+            if ((nz > 0) != (L.uz > 0)) L.dz = P.Lr - L.dz;
+            L.aiuz = MM::rcp(MM::abs_(nz));
+        }
+        L.uz = nz;
+        if (G == GEOM_EXT2D) L.ig = MM::rsqrt(nx * nx + ny * ny);
     }
     ++L.step;
     return ev;
@@ -403,8 +437,8 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     const uint64_t total_items = A.item_start[A.nprobs];
 
     Lane<R> L;
-    L.x = 0.0; L.y = L.z = L.ux = L.uy = L.uz = 0;
-    L.iux = L.iuy = L.iuz = 0; L.ig = 1;
+    L.x = 0.0; L.dy = L.dz = L.ux = L.uy = L.uz = 0;
+    L.iux = L.aiuy = L.aiuz = 0; L.ig = 1; L.fx = 0;
     L.tscore = 0.0; L.h = 0; L.hash = 0; L.step = 0;
     L.n_int = L.n_scat = L.n_lat = 0;
     L.m = 0; L.slot = 0; L.pid = 0; L.kcur = 0; L.alive = false;
@@ -419,20 +453,25 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             if (!s_open[cur] || s_next[cur] == s_cnt[cur]) {
                 const int o = cur ^ 1;
                 if (s_open[o] || queue_empty) break;
-                uint64_t item = 0;
-                if (lane == 0) item = atomicAdd((unsigned long long *)A.queue_head, 1ull);
-                item = __shfl(item, 0, 64);
+                uint64_t got = 0;
+                if (lane == 0) got = atomicAdd((unsigned long long *)A.queue_head, 1ull);
+                // lane 0's value, made wave-uniform so that the slot state
+                // derived from it stays in scalar registers
+                const uint64_t item = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(got >> 32), 0) << 32) |
+                                      (uint64_t)__builtin_amdgcn_readlane((uint32_t)got, 0);
                 if (item >= total_items) {
                     queue_empty = true;
                     break;
                 }
+                const __attribute__((address_space(4))) uint64_t *starts =
+                    (const __attribute__((address_space(4))) uint64_t *)A.item_start;
                 int lo = 0, hi = A.nprobs;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
-                    if (A.item_start[mid] <= item) lo = mid; else hi = mid;
+                    if (starts[mid] <= item) lo = mid; else hi = mid;
                 }
                 ConstProblem &P = ((ConstProblem *)A.probs)[lo];
-                const uint64_t first = (P.chunk_base + item - A.item_start[lo]) * P.chunk;
+                const uint64_t first = (P.chunk_base + item - starts[lo]) * P.chunk;
                 const uint64_t rest = P.histories - first;
                 s_h0[o] = first;
                 s_cnt[o] = (uint32_t)(rest < P.chunk ? rest : P.chunk);
@@ -472,7 +511,7 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
         uint64_t todo = ballot(L.alive);
         while (todo != 0) {
             const int first = __builtin_ctzll(todo);
-            const int pidc = __shfl(L.pid, first, 64);
+            const int pidc = __builtin_amdgcn_readlane(L.pid, first);
             const bool mine = L.alive && L.pid == pidc && ((todo >> lane) & 1ull);
             if (mine) {
                 ConstProblem *cp = (ConstProblem *)A.probs;

@@ -10,10 +10,15 @@
 // Stream layout: event step j of history h of a problem with seed s uses the
 // block at counter (j, lane, lo32(h), hi32(h)) under key (lo32(s), hi32(s));
 // lane is 0 except for the extra source block of the 3D interior source. A
-// block yields five 23-bit integers -- the top 23 bits of the four words, and
+// block yields five 23-bit integers k -- the top 23 bits of the four words, and
 // the low 9, 9 and 5 bits of words 0, 1 and 2 -- mapped to U = (k + 1/2) 2^-23,
 // a value in (0, 1) that is exact in both FP32 and FP64, so both precisions
 // see identical uniforms.
+//
+// Each k is returned as the bit pattern of the float 1 + k 2^-23 (exponent
+// field 127 above the 23 bits, one v_alignbit per word); U is that float minus
+// 1 - 2^-24, a subtraction that is exact because U = (2k + 1) 2^-24 needs at
+// most 24 significant bits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -45,19 +50,24 @@ __device__ __forceinline__ Block5 philox_u23(uint32_t step, uint32_t lane, uint6
         k1 += 0xBB67AE85u;
     }
     Block5 o;
-    o.k[0] = a >> 9;
-    o.k[1] = b >> 9;
-    o.k[2] = c >> 9;
-    o.k[3] = d >> 9;
-    o.k[4] = ((a & 0x1FFu) << 14) | ((b & 0x1FFu) << 5) | (c & 0x1Fu);
+    // (0x7F : w) >> 9 = 0x3F800000 | (w >> 9)
+    o.k[0] = __builtin_amdgcn_alignbit(0x7Fu, a, 9u);
+    o.k[1] = __builtin_amdgcn_alignbit(0x7Fu, b, 9u);
+    o.k[2] = __builtin_amdgcn_alignbit(0x7Fu, c, 9u);
+    o.k[3] = __builtin_amdgcn_alignbit(0x7Fu, d, 9u);
+    o.k[4] = 0x3F800000u | ((a & 0x1FFu) << 14) | ((b & 0x1FFu) << 5) | (c & 0x1Fu);
     return o;
 }
 
-// U = (k + 1/2) 2^-23: k * 2^-23 and the added 2^-24 are both exact.
+// U = (k + 1/2) 2^-23 from the bit pattern w of 1 + k 2^-23 (exact, see above).
 template <typename R>
-__device__ __forceinline__ R unit(uint32_t k)
+__device__ __forceinline__ R unit(uint32_t w)
 {
-    return (R)k * (R)0x1p-23 + (R)0x1p-24;
+    if constexpr (sizeof(R) == 4) {
+        return __uint_as_float(w) - (1.0f - 0x1p-24f);
+    } else {
+        return (double)__uint_as_float(w) - (1.0 - 0x1p-24);
+    }
 }
 
 }  // namespace cls
