@@ -409,6 +409,64 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
 }
 
 // ---------------------------------------------------------------------------
+// chunk slots
+// ---------------------------------------------------------------------------
+// Wave-uniform state of one chunk slot: first history, size, histories handed
+// out, histories in flight, problem, open flag.
+struct SlotState {
+    uint64_t h0;
+    uint32_t cnt, next, live;
+    int32_t pid, open;
+};
+
+// Move a finished chunk's tallies from its LDS slot to HBM: the flux bins
+// (prefix-scanned first for the difference-form track-length tally) as the
+// chunk's batch sum S and its square over the chunk size Q, the history score
+// sums and the event counters. Leaves the LDS slot zeroed and the slot closed.
+template <int EST>
+__device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, double *b, double *ssum, uint32_t *c,
+                                           int lane)
+{
+    ConstProblem &P = ((ConstProblem *)A.probs)[S.pid];
+    const int KK = P.nbins;
+    double *Sk = P.sums + 2;
+    double *Qk = P.sums + 2 + KK;
+    const double inv_n = 1.0 / (double)S.cnt;
+    double carry = 0.0;
+    for (int base = 0; base <= KK; base += 64) {
+        const int k = base + lane;
+        double v = (k <= KK) ? b[k] : 0.0;
+        if (EST == EST_TRACK) {
+            v = wave_inclusive_scan(v, lane) + carry;
+            carry = __shfl(v, 63, 64);
+        }
+        if (k < KK && v != 0.0) {
+            atomicAdd(Sk + k, v);
+            atomicAdd(Qk + k, v * v * inv_n);
+        }
+        if (k <= KK) b[k] = 0.0;
+    }
+    const double st = ssum[0];
+    const double st2 = ssum[1];
+    // one counter per lane: lanes 0..S_NCTR-1 move them to HBM
+    const uint32_t cv = lane < S_NCTR ? c[lane] : 0u;
+    if (lane < S_NCTR) c[lane] = 0u;
+    const int slot_ctr_to_global[S_NCTR] = {C_TRANSMITTED, C_REFLECTED, C_ABSORBED, C_CAPPED, C_FLIGHTS,
+                                            C_COLLISIONS, C_SCATTERS, C_INTERFACES, C_LATERAL};
+    unsigned long long *Cg = (unsigned long long *)P.counters;
+    if (lane < S_NCTR && cv != 0u) atomicAdd(Cg + slot_ctr_to_global[lane], (unsigned long long)cv);
+    if (lane == 0) {
+        ssum[0] = 0.0;
+        ssum[1] = 0.0;
+        atomicAdd(Cg + C_HISTORIES, (unsigned long long)S.cnt);
+        atomicAdd(Cg + C_BATCHES, 1ull);
+        atomicAdd(P.sums + 0, st);
+        atomicAdd(P.sums + 1, st2);
+    }
+    S.open = 0;
+}
+
+// ---------------------------------------------------------------------------
 // the tracking kernel
 // ---------------------------------------------------------------------------
 template <int G, int EST, int SRC, bool FP32, bool TRACE>
@@ -427,12 +485,12 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     uint32_t *const wctr = (uint32_t *)(wsum + 4);    // [slot][kSlotCounters]
     for (int i = lane; i < 2 * KP + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
 
-    // Wave-uniform state of the two chunk slots: first history, size,
-    // histories handed out, histories in flight, problem, open flag.
-    uint64_t s_h0[2] = {0, 0};
-    uint32_t s_cnt[2] = {0, 0}, s_next[2] = {0, 0}, s_live[2] = {0, 0};
-    int32_t s_pid[2] = {0, 0}, s_open[2] = {0, 0};
-    int cur = 0;
+    // Wave-uniform state of the two chunk slots, kept as two named records
+    // (never indexed by a run-time value, so that they stay in scalar
+    // registers): C receives new histories and owns tally buffer cp, O is the
+    // other one (buffer cp ^ 1) whose stragglers may still be in flight.
+    SlotState C = {0, 0, 0, 0, 0, 0}, O = {0, 0, 0, 0, 0, 0};
+    int cp = 0;
     bool queue_empty = false;
     const uint64_t total_items = A.item_start[A.nprobs];
 
@@ -450,9 +508,8 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
         uint64_t dead = ballot(!L.alive);
         if (dead != ~0ull && popc(dead) < (uint32_t)A.refill_min) dead = 0;
         while (dead != 0) {
-            if (!s_open[cur] || s_next[cur] == s_cnt[cur]) {
-                const int o = cur ^ 1;
-                if (s_open[o] || queue_empty) break;
+            if (!C.open || C.next == C.cnt) {
+                if (O.open || queue_empty) break;
                 uint64_t got = 0;
                 if (lane == 0) got = atomicAdd((unsigned long long *)A.queue_head, 1ull);
                 // lane 0's value, made wave-uniform so that the slot state
@@ -473,36 +530,41 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                 ConstProblem &P = ((ConstProblem *)A.probs)[lo];
                 const uint64_t first = (P.chunk_base + item - starts[lo]) * P.chunk;
                 const uint64_t rest = P.histories - first;
-                s_h0[o] = first;
-                s_cnt[o] = (uint32_t)(rest < P.chunk ? rest : P.chunk);
-                s_next[o] = 0;
-                s_live[o] = 0;
-                s_pid[o] = lo;
-                s_open[o] = 1;
-                cur = o;
+                // the new chunk goes to the free slot, which becomes current
+                O = C;
+                C.h0 = first;
+                C.cnt = (uint32_t)(rest < P.chunk ? rest : P.chunk);
+                C.next = 0;
+                C.live = 0;
+                C.pid = lo;
+                C.open = 1;
+                cp ^= 1;
                 continue;
             }
-            const uint32_t avail = s_cnt[cur] - s_next[cur];
+            const uint32_t avail = C.cnt - C.next;
             const uint32_t nd = popc(dead);
             const uint32_t take = avail < nd ? avail : nd;
             const uint32_t r = rank_in(dead);
-            if (!L.alive && r < take) {
-                L.alive = true;
-                L.slot = cur;
-                L.pid = s_pid[cur];
-                L.h = s_h0[cur] + s_next[cur] + r;
-                L.step = 0;
-                L.n_int = L.n_scat = L.n_lat = 0;
-                L.tscore = 0.0;
-                L.hash = 0xCBF29CE484222325ull;
-            }
-            s_next[cur] += take;
-            s_live[cur] += take;
+            // the r-th idle lane takes history C.h0 + C.next + r (written as
+            // selects: no branch, no copies of the lane state around one)
+            const bool nw = !L.alive && r < take;
+            L.slot = nw ? cp : L.slot;
+            L.pid = nw ? C.pid : L.pid;
+            L.h = nw ? C.h0 + C.next + r : L.h;
+            L.step = nw ? 0u : L.step;
+            L.n_int = nw ? 0u : L.n_int;
+            L.n_scat = nw ? 0u : L.n_scat;
+            L.n_lat = nw ? 0u : L.n_lat;
+            L.tscore = nw ? 0.0 : L.tscore;
+            if (TRACE) L.hash = nw ? 0xCBF29CE484222325ull : L.hash;
+            L.alive = L.alive || nw;
+            C.next += take;
+            C.live += take;
             dead = ballot(!L.alive);
         }
 
         // ---------------- exit when nothing is left --------------------------
-        if (dead == ~0ull && queue_empty && !s_open[0] && !s_open[1]) break;
+        if (dead == ~0ull && queue_empty && !C.open && !O.open) break;
 
         // ---------------- one event step per live lane -----------------------
         // A wave holds lanes of at most two problems (one per slot); each pass
@@ -514,8 +576,8 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             const int pidc = __builtin_amdgcn_readlane(L.pid, first);
             const bool mine = L.alive && L.pid == pidc && ((todo >> lane) & 1ull);
             if (mine) {
-                ConstProblem *cp = (ConstProblem *)A.probs;
-                const Prm<R> P = load_prm<R>(cp[__builtin_amdgcn_readfirstlane(pidc)]);
+                ConstProblem *cprob = (ConstProblem *)A.probs;
+                const Prm<R> P = load_prm<R>(cprob[__builtin_amdgcn_readfirstlane(pidc)]);
                 ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + L.slot * KP);
             }
             todo &= ~ballot(mine);
@@ -525,9 +587,9 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
         const bool fin = (ev == EV_LEAK_XLO) || (ev == EV_LEAK_XHI) || (ev == EV_ABSORB) || (ev == EV_CAP);
         const uint64_t m_fin = ballot(fin);
         if (m_fin) {
-            const uint64_t in1 = ballot(fin && L.slot == 1);
-            s_live[0] -= popc(m_fin & ~in1);
-            s_live[1] -= popc(m_fin & in1);
+            const uint64_t in_c = ballot(fin && L.slot == cp);
+            C.live -= popc(in_c);
+            O.live -= popc(m_fin & ~in_c);
             if (fin) {
                 double *ss = wsum + 2 * L.slot;
                 lds_add(ss, L.tscore);
@@ -553,51 +615,11 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             }
 
             // ------------- flush chunks whose last history ended -------------
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                if (s_open[s] && s_next[s] == s_cnt[s] && s_live[s] == 0) {
-                    ConstProblem &P = ((ConstProblem *)A.probs)[s_pid[s]];
-                    const int KK = P.nbins;
-                    double *b = wbuf + s * KP;
-                    double *Sk = P.sums + 2;
-                    double *Qk = P.sums + 2 + KK;
-                    const double inv_n = 1.0 / (double)s_cnt[s];
-                    double carry = 0.0;
-                    for (int base = 0; base <= KK; base += 64) {
-                        const int k = base + lane;
-                        double v = (k <= KK) ? b[k] : 0.0;
-                        if (EST == EST_TRACK) {
-                            v = wave_inclusive_scan(v, lane) + carry;
-                            carry = __shfl(v, 63, 64);
-                        }
-                        if (k < KK && v != 0.0) {
-                            atomicAdd(Sk + k, v);
-                            atomicAdd(Qk + k, v * v * inv_n);
-                        }
-                        if (k <= KK) b[k] = 0.0;
-                    }
-                    const double st = wsum[2 * s];
-                    const double st2 = wsum[2 * s + 1];
-                    uint32_t *c = wctr + s * kSlotCounters;
-                    // one counter per lane: lanes 0..S_NCTR-1 move them to HBM
-                    const uint32_t cv = lane < S_NCTR ? c[lane] : 0u;
-                    if (lane < S_NCTR) c[lane] = 0u;
-                    const int slot_ctr_to_global[S_NCTR] = {C_TRANSMITTED, C_REFLECTED, C_ABSORBED, C_CAPPED,
-                                                            C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_INTERFACES,
-                                                            C_LATERAL};
-                    unsigned long long *C = (unsigned long long *)P.counters;
-                    if (lane < S_NCTR && cv != 0u) atomicAdd(C + slot_ctr_to_global[lane], (unsigned long long)cv);
-                    if (lane == 0) {
-                        wsum[2 * s] = 0.0;
-                        wsum[2 * s + 1] = 0.0;
-                        atomicAdd(C + C_HISTORIES, (unsigned long long)s_cnt[s]);
-                        atomicAdd(C + C_BATCHES, 1ull);
-                        atomicAdd(P.sums + 0, st);
-                        atomicAdd(P.sums + 1, st2);
-                    }
-                    s_open[s] = 0;
-                }
-            }
+            if (C.open && C.next == C.cnt && C.live == 0)
+                flush_slot<EST>(C, A, wbuf + cp * KP, wsum + 2 * cp, wctr + cp * kSlotCounters, lane);
+            if (O.open && O.next == O.cnt && O.live == 0)
+                flush_slot<EST>(O, A, wbuf + (cp ^ 1) * KP, wsum + 2 * (cp ^ 1), wctr + (cp ^ 1) * kSlotCounters,
+                                lane);
         }
     }
 }
