@@ -194,7 +194,7 @@ void cls_batch_destroy(cls_batch *b);
  *   max_chunk        largest number of histories per work chunk (>= 64; default
  *                    16384); a chunk is also one batch of the flux error;
  *   refill_min       idle lanes a wave waits for before it hands out new
- *                    histories (1..64; default 1: refill every step).
+ *                    histories (1..64; default 4; 1 refills every step).
  * Values out of range give CLS_ERR_INVALID_ARG. */
 typedef struct {
     int waves_per_block;

@@ -60,7 +60,7 @@ constexpr int kDefaultBlocksPerCu = 0;     // 0: as many as fit (occupancy query
 constexpr int kDefaultMaxChunk = 16384;
 constexpr uint64_t kDefaultMaxSteps = 100000000ull;
 constexpr size_t kLdsLimit = 65536;
-constexpr int kDefaultRefillMin = 1;
+constexpr int kDefaultRefillMin = 4;
 }  // namespace
 
 namespace cls {
@@ -244,7 +244,8 @@ Variant variant_of(const cls_problem *p)
 // Launch shape. Each wave needs two LDS tally buffers; a workgroup uses at
 // most kLdsLimit. Unless the caller fixed them, the workgroup size (1, 2, 4 or
 // 8 waves) is the one that keeps the most waves resident per compute unit
-// (occupancy query; larger workgroups win ties) and the persistent grid holds
+// (occupancy query; ties go to 4, then 8, 2 and 1 waves: 4-wave workgroups
+// measured fastest at equal residency) and the persistent grid holds
 // as many workgroups as the compute units keep resident at once.
 cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
                      size_t *lds, int *lds_stride, LaunchShape *used)
@@ -256,7 +257,7 @@ cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *
     const size_t limit = std::min(kLdsLimit, di.lds_per_block ? di.lds_per_block : kLdsLimit);
     if (per_wave > limit) return fail(CLS_ERR_INVALID_ARG, "flux mesh too large for LDS");
     int best_waves = 0, best_bpc = 0;
-    const int candidates[4] = {8, 4, 2, 1};
+    const int candidates[4] = {4, 8, 2, 1};
     for (int c : candidates) {
         if (s.waves_per_block > 0 && c != s.waves_per_block) continue;
         if (per_wave * (size_t)c > limit) continue;

@@ -256,7 +256,12 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
                 L.dz = P.Lr * unit<R>(B2.k[0]);
             }
         }
-        L.kcur = bin_of<R>(L.x, P.inv_dx, P.K, &L.fx);
+        if (SRC == SRC_FACE) {
+            L.kcur = 0;      // x = 0: bin 0, offset 0
+            L.fx = 0;
+        } else {
+            L.kcur = bin_of<R>(L.x, P.inv_dx, P.K, &L.fx);
+        }
         ev = EV_SOURCE;
         if (TRACE) L.hash = fnv_event(L.hash, EV_SOURCE, L.m, L.kcur);
     } else if ((uint64_t)L.step > P.max_steps) {
@@ -336,49 +341,55 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
                 lds_add(tal + kb + 1, -pb);
             }
         }
-        // ---- the event ----
-        if (bnd) {
-            if (ax == 0) {
-                ev = L.ux > 0 ? EV_LEAK_XHI : EV_LEAK_XLO;
-            } else if (AXES >= 2 && ax == 1) {
-                ev = L.uy > 0 ? EV_REFL_YHI : EV_REFL_YLO;
-                L.uy = -L.uy;
-                L.dy = P.Lr;
-            } else {
-                ev = L.uz > 0 ? EV_REFL_ZHI : EV_REFL_ZLO;
-                L.uz = -L.uz;
-                L.dz = P.Lr;
-            }
-        } else if (!coll) {
-            ev = EV_INTERFACE;
-            L.m = 1 - mf;
-        } else {
-            if (EST == EST_COLLISION) {
+        // ---- the event (Section 4), written as selects: every lane evaluates
+        //      the same instructions whichever event it meets ----
+        const bool leak = bnd && ax == 0;
+        const bool refl_y = AXES >= 2 && bnd && ax == 1;
+        const bool refl_z = AXES >= 3 && bnd && ax == 2;
+        const bool intf = !bnd && !coll;
+        const R c_m = mf ? P.c1 : P.c0;
+        const bool scat = coll && unit<R>(B.k[2]) < c_m;
+        if (EST == EST_COLLISION) {
+            if (coll) {
                 lds_add(tal + L.kcur, (double)isig_m);
                 L.tscore += (double)isig_m;
             }
-            const R c_m = mf ? P.c1 : P.c0;
-            if (unit<R>(B.k[2]) < c_m) {
-                ev = EV_SCATTER;
-                if (G == GEOM_ROD) {
-                    L.ux = unit<R>(B.k[3]) < (R)0.5 ? (R)1 : (R)-1;
-                    L.iux = L.ux;
-                } else if (G == GEOM_SLAB) {
-                    L.ux = (R)2 * unit<R>(B.k[3]) - (R)1;
-                    L.iux = MM::rcp(L.ux);
-                    L.ig = MM::abs_(L.iux);
-                } else {
-                    need_dir = true;
-                    cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
-                    turns = unit<R>(B.k[4]);
-                }
-            } else {
-                ev = EV_ABSORB;
-            }
         }
-        L.n_int += (ev == EV_INTERFACE);
-        L.n_scat += (ev == EV_SCATTER);
-        if (AXES >= 2) L.n_lat += (ev >= EV_REFL_YLO);
+        int e = coll ? (scat ? EV_SCATTER : EV_ABSORB) : EV_INTERFACE;
+        e = leak ? (L.ux > 0 ? EV_LEAK_XHI : EV_LEAK_XLO) : e;
+        if (AXES >= 2) e = refl_y ? (L.uy > 0 ? EV_REFL_YHI : EV_REFL_YLO) : e;
+        if (AXES >= 3) e = refl_z ? (L.uz > 0 ? EV_REFL_ZHI : EV_REFL_ZLO) : e;
+        ev = e;
+        L.m = mf ^ (int)intf;
+        // a mirror reflection turns u_y (u_z) over and leaves the particle at
+        // distance L from the face it now heads for
+        if (AXES >= 2) {
+            L.uy = refl_y ? -L.uy : L.uy;
+            L.dy = refl_y ? P.Lr : L.dy;
+        }
+        if (AXES >= 3) {
+            L.uz = refl_z ? -L.uz : L.uz;
+            L.dz = refl_z ? P.Lr : L.dz;
+        }
+        // isotropic scattering: a new direction
+        if (G == GEOM_ROD) {
+            const R nu = unit<R>(B.k[3]) < (R)0.5 ? (R)1 : (R)-1;
+            L.ux = scat ? nu : L.ux;
+            L.iux = L.ux;
+        } else if (G == GEOM_SLAB) {
+            if (scat) {
+                L.ux = (R)2 * unit<R>(B.k[3]) - (R)1;
+                L.iux = MM::rcp(L.ux);
+                L.ig = MM::abs_(L.iux);
+            }
+        } else {
+            need_dir = scat;
+            cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
+            turns = unit<R>(B.k[4]);
+        }
+        L.n_int += intf ? 1u : 0u;
+        L.n_scat += scat ? 1u : 0u;
+        if (AXES >= 2) L.n_lat += (refl_y || refl_z) ? 1u : 0u;
         if (TRACE) L.hash = fnv_event(L.hash, ev, mf, L.kcur);
     }
     // ---- shared direction sampler: polar axis x for the inward cosine-law
