@@ -205,6 +205,8 @@ void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, u
         out->isigf[i] = (float)out->isig[i];
         out->cf[i] = (float)p->c[i];
         out->lamf[i] = (float)p->lam[i];
+        out->dsigf[i] = (float)(-0.69314718055994530942 / p->sigma[i]);
+        out->dlamf[i] = (float)(-0.69314718055994530942 * p->lam[i]);
     }
     out->seed = seed;
     out->histories = histories;

@@ -47,6 +47,9 @@ struct alignas(16) DevProblem {
     // FP32 copies for the FP32 tracking kernel
     float Lf, p0f;
     float isigf[2], cf[2], lamf[2];
+    // FP32 flight-distance scales: a distance is log2(U) times -ln2 / Sigma_i
+    // (collision) or -ln2 Lambda_i (interface)
+    float dsigf[2], dlamf[2];
     uint64_t seed;
     uint64_t histories;
     uint64_t chunk;             // histories per work item (batch)

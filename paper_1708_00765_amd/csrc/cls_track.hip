@@ -41,11 +41,9 @@ struct Math;
 
 template <>
 struct Math<float> {
-    // -ln(u) for u in (0, 1): hardware log2 times ln 2
-    static __device__ __forceinline__ float neglog(float u)
-    {
-        return __builtin_amdgcn_logf(u) * -0.693147180559945309f;
-    }
+    // the logarithm a flight distance is scaled from: hardware log2 (the
+    // distance scales carry the factor -ln 2)
+    static __device__ __forceinline__ float dlog(float u) { return __builtin_amdgcn_logf(u); }
     static __device__ __forceinline__ float sqrt_(float v) { return __builtin_amdgcn_sqrtf(v); }
     static __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
     static __device__ __forceinline__ float rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
@@ -61,7 +59,8 @@ struct Math<float> {
 
 template <>
 struct Math<double> {
-    static __device__ __forceinline__ double neglog(double u) { return -log(u); }
+    // -ln(u): the distance scales are 1/Sigma_i and Lambda_i themselves
+    static __device__ __forceinline__ double dlog(double u) { return -log(u); }
     static __device__ __forceinline__ double sqrt_(double v) { return sqrt(v); }
     static __device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
     static __device__ __forceinline__ double rsqrt(double v) { return 1.0 / sqrt(v); }
@@ -128,7 +127,8 @@ static_assert(S_NCTR <= kSlotCounters, "slot counters do not fit their LDS area"
 // lane otherwise (a wave straddling two work chunks of different problems).
 template <typename R>
 struct Prm {
-    R isig0, isig1, c0, c1, lam0, lam1, p0, Lr, dxr;
+    R isig0, isig1, c0, c1, p0, Lr, dxr;
+    R ds0, ds1, dl0, dl1;    // flight-distance scales (collision, interface) per material
     double Ld, inv_dx, dx;
     int K;
     uint32_t key_lo, key_hi;
@@ -149,12 +149,14 @@ __device__ __forceinline__ Prm<R> load_prm(ConstProblem &P)
     if constexpr (std::is_same<R, float>::value) {
         q.isig0 = P.isigf[0]; q.isig1 = P.isigf[1];
         q.c0 = P.cf[0]; q.c1 = P.cf[1];
-        q.lam0 = P.lamf[0]; q.lam1 = P.lamf[1];
+        q.ds0 = P.dsigf[0]; q.ds1 = P.dsigf[1];
+        q.dl0 = P.dlamf[0]; q.dl1 = P.dlamf[1];
         q.p0 = P.p0f; q.Lr = P.Lf; q.dxr = P.dxf;
     } else {
         q.isig0 = P.isig[0]; q.isig1 = P.isig[1];
         q.c0 = P.c[0]; q.c1 = P.c[1];
-        q.lam0 = P.lam[0]; q.lam1 = P.lam[1];
+        q.ds0 = P.isig[0]; q.ds1 = P.isig[1];
+        q.dl0 = P.lam[0]; q.dl1 = P.lam[1];
         q.p0 = P.p0; q.Lr = P.L; q.dxr = P.dx;
     }
     q.Ld = P.L; q.inv_dx = P.inv_dx; q.dx = P.dx; q.K = P.nbins;
@@ -270,10 +272,8 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
     } else {
         // ---- flight: three distances, the smallest wins (Section 4) ----
         const int mf = L.m;
-        const R isig_m = mf ? P.isig1 : P.isig0;
-        const R lam_m = mf ? P.lam1 : P.lam0;
-        const R lc = MM::neglog(unit<R>(B.k[0])) * isig_m;
-        const R li = MM::neglog(unit<R>(B.k[1])) * lam_m * L.ig;
+        const R lc = MM::dlog(unit<R>(B.k[0])) * (mf ? P.ds1 : P.ds0);
+        const R li = MM::dlog(unit<R>(B.k[1])) * (mf ? P.dl1 : P.dl0) * L.ig;
         // distance to the box: |distance to the face headed for| / |u| per
         // axis; a direction parallel to an axis gives +inf (or NaN for a
         // particle on that face), which never wins
@@ -298,7 +298,10 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         L.x += (double)(s * L.ux);
         if (AXES >= 2) L.dy = MM::fma_(-s, MM::abs_(L.uy), L.dy);
         if (AXES >= 3) L.dz = MM::fma_(-s, MM::abs_(L.uz), L.dz);
-        if (bnd && ax == 0) L.x = L.ux > 0 ? P.Ld : 0.0;
+        // FP64 puts a leaking particle exactly on its face; in FP32 the
+        // history ends there anyway and the snap would only move the last
+        // track-length partial by a rounding error
+        if (!FP32 && bnd && ax == 0) L.x = L.ux > 0 ? P.Ld : 0.0;
         // A lateral coordinate rounded past its face is harmless: the next
         // distance to that face is <= 0, so the particle reaches it at once.
         L.kcur = bin_of<R>(L.x, P.inv_dx, P.K, &L.fx);
@@ -351,6 +354,7 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         const bool scat = coll && unit<R>(B.k[2]) < c_m;
         if (EST == EST_COLLISION) {
             if (coll) {
+                const R isig_m = mf ? P.isig1 : P.isig0;
                 lds_add(tal + L.kcur, (double)isig_m);
                 L.tscore += (double)isig_m;
             }
@@ -387,9 +391,9 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
             cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
             turns = unit<R>(B.k[4]);
         }
-        L.n_int += intf ? 1u : 0u;
-        L.n_scat += scat ? 1u : 0u;
-        if (AXES >= 2) L.n_lat += (refl_y || refl_z) ? 1u : 0u;
+        L.n_int += (uint32_t)intf;
+        L.n_scat += (uint32_t)scat;
+        if (AXES >= 2) L.n_lat += (uint32_t)(refl_y || refl_z);
         if (TRACE) L.hash = fnv_event(L.hash, ev, mf, L.kcur);
     }
     // ---- shared direction sampler: polar axis x for the inward cosine-law
