@@ -185,6 +185,7 @@ struct Lane {
     uint32_t step;
     uint32_t n_int, n_scat, n_lat;   // this history's interface crossings, scatters, lateral reflections
     int m, slot, pid, kcur;  // material, chunk slot, problem, bin of x
+    int tb;                  // offset of the slot's LDS tally buffer (doubles)
     bool alive;
 };
 
@@ -514,17 +515,18 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     L.iux = L.aiuy = L.aiuz = 0; L.ig = 1; L.fx = 0;
     L.tscore = 0.0; L.h = 0; L.hash = 0; L.step = 0;
     L.n_int = L.n_scat = L.n_lat = 0;
-    L.m = 0; L.slot = 0; L.pid = 0; L.kcur = 0; L.alive = false;
+    L.m = 0; L.slot = 0; L.pid = 0; L.kcur = 0; L.tb = 0; L.alive = false;
 
     for (;;) {
         // ---------------- hand out histories to idle lanes ----------------
         // Idle lanes are refilled once at least refill_min of them wait (or the
         // whole wave is idle): fewer, fuller source steps against idle lanes.
+        // At most one hand-out per step: when the current chunk runs out, a
+        // new one is claimed first (if the other slot is free); idle lanes the
+        // chunk cannot serve wait for the next step.
         uint64_t dead = ballot(!L.alive);
-        if (dead != ~0ull && popc(dead) < (uint32_t)A.refill_min) dead = 0;
-        while (dead != 0) {
-            if (!C.open || C.next == C.cnt) {
-                if (O.open || queue_empty) break;
+        if (dead != 0 && (dead == ~0ull || popc(dead) >= (uint32_t)A.refill_min)) {
+            if ((!C.open || C.next == C.cnt) && !O.open && !queue_empty) {
                 uint64_t got = 0;
                 if (lane == 0) got = atomicAdd((unsigned long long *)A.queue_head, 1ull);
                 // lane 0's value, made wave-uniform so that the slot state
@@ -533,49 +535,51 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                                       (uint64_t)__builtin_amdgcn_readlane((uint32_t)got, 0);
                 if (item >= total_items) {
                     queue_empty = true;
-                    break;
+                } else {
+                    const __attribute__((address_space(4))) uint64_t *starts =
+                        (const __attribute__((address_space(4))) uint64_t *)A.item_start;
+                    int lo = 0, hi = A.nprobs;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (starts[mid] <= item) lo = mid; else hi = mid;
+                    }
+                    ConstProblem &P = ((ConstProblem *)A.probs)[lo];
+                    const uint64_t first = (P.chunk_base + item - starts[lo]) * P.chunk;
+                    const uint64_t rest = P.histories - first;
+                    // the new chunk goes to the free slot, which becomes current
+                    O = C;
+                    C.h0 = first;
+                    C.cnt = (uint32_t)(rest < P.chunk ? rest : P.chunk);
+                    C.next = 0;
+                    C.live = 0;
+                    C.pid = lo;
+                    C.open = 1;
+                    cp ^= 1;
                 }
-                const __attribute__((address_space(4))) uint64_t *starts =
-                    (const __attribute__((address_space(4))) uint64_t *)A.item_start;
-                int lo = 0, hi = A.nprobs;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (starts[mid] <= item) lo = mid; else hi = mid;
-                }
-                ConstProblem &P = ((ConstProblem *)A.probs)[lo];
-                const uint64_t first = (P.chunk_base + item - starts[lo]) * P.chunk;
-                const uint64_t rest = P.histories - first;
-                // the new chunk goes to the free slot, which becomes current
-                O = C;
-                C.h0 = first;
-                C.cnt = (uint32_t)(rest < P.chunk ? rest : P.chunk);
-                C.next = 0;
-                C.live = 0;
-                C.pid = lo;
-                C.open = 1;
-                cp ^= 1;
-                continue;
             }
-            const uint32_t avail = C.cnt - C.next;
-            const uint32_t nd = popc(dead);
-            const uint32_t take = avail < nd ? avail : nd;
-            const uint32_t r = rank_in(dead);
-            // the r-th idle lane takes history C.h0 + C.next + r (written as
-            // selects: no branch, no copies of the lane state around one)
-            const bool nw = !L.alive && r < take;
-            L.slot = nw ? cp : L.slot;
-            L.pid = nw ? C.pid : L.pid;
-            L.h = nw ? C.h0 + C.next + r : L.h;
-            L.step = nw ? 0u : L.step;
-            L.n_int = nw ? 0u : L.n_int;
-            L.n_scat = nw ? 0u : L.n_scat;
-            L.n_lat = nw ? 0u : L.n_lat;
-            L.tscore = nw ? 0.0 : L.tscore;
-            if (TRACE) L.hash = nw ? 0xCBF29CE484222325ull : L.hash;
-            L.alive = L.alive || nw;
-            C.next += take;
-            C.live += take;
-            dead = ballot(!L.alive);
+            if (C.open && C.next < C.cnt) {
+                const uint32_t avail = C.cnt - C.next;
+                const uint32_t nd = popc(dead);
+                const uint32_t take = avail < nd ? avail : nd;
+                const uint32_t r = rank_in(dead);
+                // the r-th idle lane takes history C.h0 + C.next + r (written as
+                // selects: no branch, no copies of the lane state around one)
+                const bool nw = !L.alive && r < take;
+                L.slot = nw ? cp : L.slot;
+                L.tb = nw ? cp * KP : L.tb;
+                L.pid = nw ? C.pid : L.pid;
+                L.h = nw ? C.h0 + C.next + r : L.h;
+                L.step = nw ? 0u : L.step;
+                L.n_int = nw ? 0u : L.n_int;
+                L.n_scat = nw ? 0u : L.n_scat;
+                L.n_lat = nw ? 0u : L.n_lat;
+                L.tscore = nw ? 0.0 : L.tscore;
+                if (TRACE) L.hash = nw ? 0xCBF29CE484222325ull : L.hash;
+                L.alive = L.alive || nw;
+                C.next += take;
+                C.live += take;
+                dead = ballot(!L.alive);
+            }
         }
 
         // ---------------- exit when nothing is left --------------------------
@@ -593,7 +597,7 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             if (mine) {
                 ConstProblem *cprob = (ConstProblem *)A.probs;
                 const Prm<R> P = load_prm<R>(cprob[__builtin_amdgcn_readfirstlane(pidc)]);
-                ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + L.slot * KP);
+                ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + L.tb);
             }
             todo &= ~ballot(mine);
         }
