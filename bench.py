@@ -54,8 +54,96 @@ def run_batch_steps(cls, torch, probs, specs, steps, warmup, seed_salt):
         track_ms += t.track_ms
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    tallies = [cls.cls_read_tallies(p, s.nbins)[0] for p, s in zip(probs, specs)]
-    return wall, track_ms, tallies
+    full = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(probs, specs)]
+    return wall, track_ms, full
+
+
+def crn_deviation(full32, full64):
+    """FP32 vs FP64 tallies of the same histories (common random numbers): the
+    largest relative deviation over the sets of T, R and the total flux, of the
+    flux profile as a whole (L2 norm of the bin differences over that of the
+    FP64 bins), of the worst single bin (bins with a nonzero FP64 value), the
+    share of the total flux carried by bins deviating by more than 1e-4, and the
+    largest deviation of any of them in FP64 standard deviations."""
+    import numpy as np
+    rel_s = rel_b = rel_l2 = sig = share = 0.0
+    for (t32, f32, _), (t64, f64, s64) in zip(full32, full64):
+        for k, sk in (("T", "sigma_T"), ("R", "sigma_R"), ("total_flux", "sigma_total_flux")):
+            a, b, sg = getattr(t64, k), getattr(t32, k), getattr(t64, sk)
+            if a != 0.0:
+                rel_s = max(rel_s, abs(b - a) / abs(a))
+            if sg > 0.0:
+                sig = max(sig, abs(b - a) / sg)
+        nz = f64 != 0.0
+        if nz.any():
+            rb = np.abs(f32[nz] - f64[nz]) / np.abs(f64[nz])
+            rel_b = max(rel_b, float(rb.max()))
+            share = max(share, float(np.abs(f64[nz][rb > 1e-4]).sum() / np.abs(f64).sum()))
+            rel_l2 = max(rel_l2, float(np.linalg.norm(f32 - f64) / np.linalg.norm(f64)))
+        ok = s64 > 0.0
+        if ok.any():
+            sig = max(sig, float(np.max(np.abs(f32[ok] - f64[ok]) / s64[ok])))
+    return {"max_rel_scalar": rel_s, "max_rel_profile_l2": rel_l2, "max_rel_bin": rel_b,
+            "flux_share_of_bins_beyond_1e-4": share, "max_sigma": sig,
+            "compared": "T, R, total flux and every flux bin of each set"}
+
+
+def load_paper_rows():
+    """The CLS rows of Tables 3-8 (printed values, one-sigma errors and t_tot)."""
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_cls_rows.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "I":
+            vals = {"R": (float(f[3]), float(f[4])), "T": (float(f[5]), float(f[6])),
+                    "flux": (float(f[7]), float(f[8]))}
+            t_tot = float(f[9])
+        else:
+            vals = {"Lk": (float(f[3]), float(f[4])), "flux": (float(f[5]), float(f[6]))}
+            t_tot = float(f[7])
+        rows.append((f[0], f[1], int(f[2]), vals, t_tot, f[-1]))
+    return rows
+
+
+def run_paper_rows(cls, torch, stream, histories, fp32):
+    """Every CLS row of Tables 3-8 as one plain run of `histories` histories:
+    the paper's observables (suite I: R, T, <phi>; suite II: the leakage
+    <(T+R)/2> and <phi>) against the printed values, in combined standard
+    deviations, and the GPU time of the run against the printed t_tot."""
+    import math
+    from paper_1708_00765_amd.inputs import paper_case
+    out = []
+    for i, (suite, case, d, vals, t_tot, table) in enumerate(load_paper_rows()):
+        s = paper_case(case, d, suite, histories=histories, seed=770000 + i)
+        p = make_problem(cls, s, fp32)
+        cls.cls_set_stream(p, stream)
+        cls.cls_run(p, min(histories, 100_000), s.seed + 1)      # warm the code object
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cls.cls_run(p, histories, s.seed)
+        t, _, _ = cls.cls_read_tallies(p, s.nbins)
+        wall = time.perf_counter() - t0
+        cls.cls_destroy_problem(p)
+        n = t.histories
+        if suite == "I":
+            obs = {"R": (t.R, t.sigma_R), "T": (t.T, t.sigma_T), "flux": (t.total_flux, t.sigma_total_flux)}
+        else:
+            leaked = t.transmitted + t.reflected
+            mean = 0.5 * leaked / n
+            var = (0.25 * leaked / n - mean * mean) * n / (n - 1)
+            obs = {"Lk": (mean, math.sqrt(max(var, 0.0) / n)), "flux": (t.total_flux, t.sigma_total_flux)}
+        zs = {}
+        for k, (v, sv) in vals.items():
+            m, sm = obs[k]
+            zs[k] = (m - v) / math.sqrt(sm * sm + sv * sv)
+        out.append({"table": table, "suite": suite, "case": case, "d": d, "histories": n,
+                    "ours": {k: obs[k][0] for k in vals}, "ours_sigma": {k: obs[k][1] for k in vals},
+                    "paper": {k: vals[k][0] for k in vals}, "z": zs,
+                    "gpu_s": wall, "kernel_s": t.track_ms * 1e-3, "paper_t_tot_s": t_tot})
+        log(f"  {table} {suite:2s} {case} d={d}: " + ", ".join(f"{k} z={zs[k]:+.2f}" for k in zs)
+            + f"; {wall:.2f} s (paper t_tot {t_tot:.3g} s)")
+    return out
 
 
 def run_ext2d_comparison(cls, torch, stream, steps):
@@ -149,6 +237,10 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
     ap.add_argument("--ext2d-steps", type=int, default=2,
                     help="timed passes of the 256-set ext2d comparison (0 = skip)")
+    ap.add_argument("--paper-rows", type=float, default=0,
+                    help="histories per row for the 54 CLS rows of Tables 3-8 (0 = skip; the paper used 1e9)")
+    ap.add_argument("--paper-precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--paper-out", default="", help="write the per-row results of --paper-rows to this JSON file")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -174,7 +266,9 @@ def main() -> int:
         cls.cls_set_stream(p, stream)
     log(f"fp32 batched: {len(specs)} sets x {specs[0].histories:.3g} histories, "
         f"{args.warmup} warmup + {args.steps} steps")
-    wall, track_ms, tallies = run_batch_steps(cls, torch, probs, specs, args.steps, args.warmup, 0)
+    wall, track_ms, full32 = run_batch_steps(cls, torch, probs, specs, args.steps, args.warmup, 0)
+    tallies = [f[0] for f in full32]
+    last_step = args.warmup + args.steps - 1      # seed index of the last timed FP32 step
     ms_per_step = 1e3 * wall / args.steps
     value = total_hist * args.steps / wall
     flights = sum(t.flights for t in tallies)
@@ -202,16 +296,27 @@ def main() -> int:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         k64 = 0.0
+        full64 = None
         for k in range(args.fp64_steps):
+            # the first pass uses the seeds of the last timed FP32 step: common
+            # random numbers, so the two results differ only by the precision
             for p, s in zip(probs64, specs):
-                cls.cls_run(p, s.histories, (s.seed + 0x9E3779B97F4A7C15 * (k + 1)) & (2**64 - 1))
+                cls.cls_run(p, s.histories, (s.seed + 0x9E3779B97F4A7C15 * (last_step + k)) & (2**64 - 1))
                 k64 += cls.cls_read_tallies(p, s.nbins)[0].track_ms
+            if k == 0:
+                full64 = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(probs64, specs)]
         torch.cuda.synchronize()
         w64 = time.perf_counter() - t0
         v64 = total_hist * args.fp64_steps / w64
         fp64 = {"value": v64, "unit": "histories/s", "ms_per_step": 1e3 * w64 / args.fp64_steps,
                 "kernel_ms_per_step": k64 / args.fp64_steps, "launches_per_step": len(specs)}
-        log(f"fp64 plain: {fp64['ms_per_step']:.1f} ms/step, {v64:.4g} hist/s")
+        fp64["fp32_deviation"] = crn_deviation(full32, full64)
+        log(f"fp64 plain: {fp64['ms_per_step']:.1f} ms/step, {v64:.4g} hist/s; fp32 vs fp64 (same seeds): "
+            f"max rel dev T/R/flux {fp64['fp32_deviation']['max_rel_scalar']:.2e}, "
+            f"profile L2 {fp64['fp32_deviation']['max_rel_profile_l2']:.2e}, "
+            f"worst bin {fp64['fp32_deviation']['max_rel_bin']:.2e} "
+            f"(bins beyond 1e-4 carry {fp64['fp32_deviation']['flux_share_of_bins_beyond_1e-4']:.2e} of the flux), "
+            f"{fp64['fp32_deviation']['max_sigma']:.2f} sigma")
         for p in probs64:
             cls.cls_destroy_problem(p)
 
@@ -234,6 +339,22 @@ def main() -> int:
         served = run_served(cls, args.serve_seconds, args.serve_rate)
         log(f"served: {served['completed']} requests, p50 {served['p50_ms']:.1f} ms, "
             f"p99 {served['p99_ms']:.1f} ms, {served['histories_per_s']:.4g} hist/s")
+
+    # ---- the paper's own benchmark rows ---------------------------------------
+    paper = None
+    if args.paper_rows > 0:
+        log(f"paper rows: 54 CLS rows of Tables 3-8, {args.paper_rows:.3g} histories each, {args.paper_precision}")
+        rows = run_paper_rows(cls, torch, stream, int(args.paper_rows), args.paper_precision == "fp32")
+        zmax = max(abs(v) for r in rows for v in r["z"].values())
+        paper = {"rows": len(rows), "histories_per_row": int(args.paper_rows), "precision": args.paper_precision,
+                 "max_abs_z": zmax, "beyond_4_sigma": sum(1 for r in rows for v in r["z"].values() if abs(v) >= 4),
+                 "gpu_seconds": sum(r["gpu_s"] for r in rows),
+                 "paper_t_tot_seconds": sum(r["paper_t_tot_s"] for r in rows)}
+        log(f"paper rows: max |z| {zmax:.2f}, {paper['beyond_4_sigma']} beyond 4 sigma, GPU "
+            f"{paper['gpu_seconds']:.1f} s vs paper t_tot {paper['paper_t_tot_seconds']:.3g} s")
+        if args.paper_out:
+            with open(args.paper_out, "w") as f:
+                json.dump({"summary": paper, "rows": rows}, f, indent=1)
 
     # ---- CPU oracle on a bounded sample ---------------------------------------
     cpu = None
@@ -291,6 +412,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "served": served,
         "ext2d_batched_vs_fp64_plain": ext2d,
+        "paper_rows": paper,
     }
     print(json.dumps(line), flush=True)
     return 0
