@@ -58,6 +58,33 @@ def run_batch_steps(cls, torch, probs, specs, steps, warmup, seed_salt):
     return wall, track_ms, full
 
 
+def kernel_source_sha256():
+    """Hash of the tracking kernel's sources (the kernel and the headers it includes)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("cls_track.hip", "cls_internal.hpp", "philox.hpp"):
+        with open(os.path.join(ROOT, "paper_1708_00765_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per tracking launch of this workload from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "track_kernel_cube3d_track_traffic.md")
+    if not os.path.exists(path):
+        return None
+    keys = {}
+    for line in open(path):
+        parts = line.strip().split(":", 1)
+        if len(parts) == 2 and parts[0] in ("kernel_source_sha256", "traffic_bytes_per_launch"):
+            keys[parts[0]] = parts[1].strip()
+    if keys.get("kernel_source_sha256") != kernel_source_sha256() or "traffic_bytes_per_launch" not in keys:
+        return None
+    return float(keys["traffic_bytes_per_launch"])
+
+
 def crn_deviation(full32, full64):
     """FP32 vs FP64 tallies of the same histories (common random numbers): the
     largest relative deviation over the sets of T, R and the total flux, of the
@@ -383,6 +410,7 @@ def main() -> int:
                          f"({tc:.1f} s, FP64, OpenMP over 4096-history chunks)"}
         log(f"cpu oracle: {cpu['value']:.4g} hist/s on {cpu['cores']} threads")
 
+    traffic = measured_traffic() if args.workload == "cube3d_track" and not args.histories else None
     line = {
         "metric": "histories/s on 1 MI355X, FP32-batched vs plain FP64 CLS; p50/p99 req latency",
         "value": value,
@@ -407,7 +435,9 @@ def main() -> int:
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per tracking launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                     "traffic_gb_per_s": (traffic / (kernel_ms * 1e-3) / 1e9) if traffic else None,
                      "kernel_ms": kernel_ms, "algorithmic_slots_per_launch": slots},
         "cpu_baseline": cpu,
         "served": served,
