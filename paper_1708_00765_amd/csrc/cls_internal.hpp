@@ -78,7 +78,10 @@ struct TrackArgs {
 // LDS per wave beyond its two tally buffers: score sums of the two slots
 // (4 doubles) and kSlotCounters 32-bit counters per slot.
 constexpr int kSlotCounters = 12;
-constexpr int kWaveExtraDoubles = 4 + kSlotCounters;
+// ... then the per-material flight parameters of the problem each slot holds:
+// 2 slots x 2 materials x 4 values, room for FP64 values.
+constexpr int kMatTableDoubles = 16;
+constexpr int kWaveExtraDoubles = 4 + kSlotCounters + kMatTableDoubles;
 
 struct LaunchShape {
     int waves_per_block;

@@ -121,14 +121,16 @@ __device__ __forceinline__ uint64_t fnv_event(uint64_t h, int ev, int m, int bin
 // ---------------------------------------------------------------------------
 enum SlotCtr : int { S_T = 0, S_R, S_A, S_CAP, S_FLIGHTS, S_COLL, S_SCAT, S_INT, S_LAT, S_NCTR };
 static_assert(S_NCTR <= kSlotCounters, "slot counters do not fit their LDS area");
+static_assert(EV_LEAK_XHI - EV_LEAK_XHI == S_T && EV_LEAK_XHI - EV_LEAK_XLO == S_R &&
+                  EV_LEAK_XHI - EV_ABSORB == S_A,
+              "outcome counters follow the leak and absorption event codes");
 
 // Problem parameters used by an event step. Loaded each step: with scalar
 // loads (SGPRs) when every live lane of the wave tracks the same problem, per
 // lane otherwise (a wave straddling two work chunks of different problems).
 template <typename R>
 struct Prm {
-    R isig0, isig1, c0, c1, p0, Lr, dxr;
-    R ds0, ds1, dl0, dl1;    // flight-distance scales (collision, interface) per material
+    R p0, Lr, dxr;
     double Ld, inv_dx, dx;
     int K;
     uint32_t key_lo, key_hi;
@@ -147,16 +149,8 @@ __device__ __forceinline__ Prm<R> load_prm(ConstProblem &P)
 {
     Prm<R> q;
     if constexpr (std::is_same<R, float>::value) {
-        q.isig0 = P.isigf[0]; q.isig1 = P.isigf[1];
-        q.c0 = P.cf[0]; q.c1 = P.cf[1];
-        q.ds0 = P.dsigf[0]; q.ds1 = P.dsigf[1];
-        q.dl0 = P.dlamf[0]; q.dl1 = P.dlamf[1];
         q.p0 = P.p0f; q.Lr = P.Lf; q.dxr = P.dxf;
     } else {
-        q.isig0 = P.isig[0]; q.isig1 = P.isig[1];
-        q.c0 = P.c[0]; q.c1 = P.c[1];
-        q.ds0 = P.isig[0]; q.ds1 = P.isig[1];
-        q.dl0 = P.lam[0]; q.dl1 = P.lam[1];
         q.p0 = P.p0; q.Lr = P.L; q.dxr = P.dx;
     }
     q.Ld = P.L; q.inv_dx = P.inv_dx; q.dx = P.dx; q.K = P.nbins;
@@ -164,6 +158,29 @@ __device__ __forceinline__ Prm<R> load_prm(ConstProblem &P)
     q.trace_n = P.trace_n; q.max_steps = P.max_steps;
     q.trace_hash = P.trace_hash; q.trace_len = P.trace_len;
     return q;
+}
+
+// Flight parameters of one material of a problem, kept per chunk slot in LDS
+// (written when the slot takes a chunk): the collision and interface distance
+// scales (FP32: -ln2 / Sigma_i and -ln2 Lambda_i, applied to log2 U; FP64:
+// 1 / Sigma_i and Lambda_i, applied to -ln U), the scattering ratio c_i and
+// 1 / Sigma_i. A flight reads its material's row with one LDS load instead of
+// selecting four values between the two materials.
+template <typename R>
+struct alignas(16) MatRow {
+    R ds, dl, c, isig;
+};
+
+template <typename R>
+__device__ __forceinline__ MatRow<R> mat_row(ConstProblem &P, int m)
+{
+    MatRow<R> r;
+    if constexpr (std::is_same<R, float>::value) {
+        r.ds = P.dsigf[m]; r.dl = P.dlamf[m]; r.c = P.cf[m]; r.isig = P.isigf[m];
+    } else {
+        r.ds = P.isig[m]; r.dl = P.lam[m]; r.c = P.c[m]; r.isig = P.isig[m];
+    }
+    return r;
 }
 
 // Per-lane particle state. The lateral coordinates are kept as the distance
@@ -204,7 +221,7 @@ __device__ __forceinline__ int bin_of(double x, double inv_dx, int K, R *frac)
 // One event step of one lane: the source (step 0) or a flight. Returns the
 // event code. `tal` is the lane's LDS tally buffer.
 template <int G, int EST, int SRC, bool FP32, bool TRACE, typename R>
-__device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *tal)
+__device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *tal, const MatRow<R> *mtab)
 {
     using MM = Math<R>;
     constexpr int AXES = (G == GEOM_EXT2D) ? 2 : (G == GEOM_CUBE3D ? 3 : 1);
@@ -273,8 +290,9 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
     } else {
         // ---- flight: three distances, the smallest wins (Section 4) ----
         const int mf = L.m;
-        const R lc = MM::dlog(unit<R>(B.k[0])) * (mf ? P.ds1 : P.ds0);
-        const R li = MM::dlog(unit<R>(B.k[1])) * (mf ? P.dl1 : P.dl0) * L.ig;
+        const MatRow<R> mat = mtab[mf];
+        const R lc = MM::dlog(unit<R>(B.k[0])) * mat.ds;
+        const R li = MM::dlog(unit<R>(B.k[1])) * mat.dl * L.ig;
         // distance to the box: |distance to the face headed for| / |u| per
         // axis; a direction parallel to an axis gives +inf (or NaN for a
         // particle on that face), which never wins
@@ -351,13 +369,11 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         const bool refl_y = AXES >= 2 && bnd && ax == 1;
         const bool refl_z = AXES >= 3 && bnd && ax == 2;
         const bool intf = !bnd && !coll;
-        const R c_m = mf ? P.c1 : P.c0;
-        const bool scat = coll && unit<R>(B.k[2]) < c_m;
+        const bool scat = coll && unit<R>(B.k[2]) < mat.c;
         if (EST == EST_COLLISION) {
             if (coll) {
-                const R isig_m = mf ? P.isig1 : P.isig0;
-                lds_add(tal + L.kcur, (double)isig_m);
-                L.tscore += (double)isig_m;
+                lds_add(tal + L.kcur, (double)mat.isig);
+                L.tscore += (double)mat.isig;
             }
         }
         int e = coll ? (scat ? EV_SCATTER : EV_ABSORB) : EV_INTERFACE;
@@ -499,6 +515,7 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     double *const wbuf = lds + (size_t)wid * (2u * (size_t)KP + kWaveExtraDoubles);
     double *const wsum = wbuf + 2 * KP;
     uint32_t *const wctr = (uint32_t *)(wsum + 4);    // [slot][kSlotCounters]
+    MatRow<R> *const wmat = (MatRow<R> *)(wsum + 4 + kSlotCounters);   // [slot][material]
     for (int i = lane; i < 2 * KP + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
 
     // Wave-uniform state of the two chunk slots, kept as two named records
@@ -555,6 +572,10 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                     C.pid = lo;
                     C.open = 1;
                     cp ^= 1;
+                    // the new slot's material rows; no lane of this wave reads
+                    // them before its next event step, and a wave's LDS
+                    // operations complete in order
+                    if (lane < 2) wmat[2 * cp + lane] = mat_row<R>(P, lane);
                 }
             }
             if (C.open && C.next < C.cnt) {
@@ -597,7 +618,7 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             if (mine) {
                 ConstProblem *cprob = (ConstProblem *)A.probs;
                 const Prm<R> P = load_prm<R>(cprob[__builtin_amdgcn_readfirstlane(pidc)]);
-                ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + L.tb);
+                ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + L.tb, wmat + 2 * L.slot);
             }
             todo &= ~ballot(mine);
         }
@@ -614,7 +635,9 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                 lds_add(ss, L.tscore);
                 lds_add(ss + 1, L.tscore * L.tscore);
                 uint32_t *c = wctr + L.slot * kSlotCounters;
-                const int outcome = ev == EV_LEAK_XHI ? S_T : (ev == EV_LEAK_XLO ? S_R : (ev == EV_ABSORB ? S_A : S_CAP));
+                // leak at x = L, leak at x = 0, absorption -> T, R, A (consecutive
+                // event codes in reverse order), the cap -> CAP
+                const int outcome = ev == EV_CAP ? S_CAP : EV_LEAK_XHI - ev;
                 atomicAdd(c + outcome, 1u);
                 // steps = source + flights (+ the refused step of a capped history)
                 const uint32_t flights = L.step - 1u - (ev == EV_CAP ? 1u : 0u);
