@@ -378,8 +378,12 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         }
         int e = coll ? (scat ? EV_SCATTER : EV_ABSORB) : EV_INTERFACE;
         e = leak ? (L.ux > 0 ? EV_LEAK_XHI : EV_LEAK_XLO) : e;
-        if (AXES >= 2) e = refl_y ? (L.uy > 0 ? EV_REFL_YHI : EV_REFL_YLO) : e;
-        if (AXES >= 3) e = refl_z ? (L.uz > 0 ? EV_REFL_ZHI : EV_REFL_ZLO) : e;
+        if (TRACE) {
+            // the exact event enters the trace hash; without a trace only the
+            // ends of a history (leaks, absorption) need telling apart
+            if (AXES >= 2) e = refl_y ? (L.uy > 0 ? EV_REFL_YHI : EV_REFL_YLO) : e;
+            if (AXES >= 3) e = refl_z ? (L.uz > 0 ? EV_REFL_ZHI : EV_REFL_ZLO) : e;
+        }
         ev = e;
         L.m = mf ^ (int)intf;
         // a mirror reflection turns u_y (u_z) over and leaves the particle at
@@ -624,7 +628,8 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
         }
 
         // ---------------- histories that ended -------------------------------
-        const bool fin = (ev == EV_LEAK_XLO) || (ev == EV_LEAK_XHI) || (ev == EV_ABSORB) || (ev == EV_CAP);
+        constexpr uint32_t kEnds = (1u << EV_LEAK_XLO) | (1u << EV_LEAK_XHI) | (1u << EV_ABSORB) | (1u << EV_CAP);
+        const bool fin = ((kEnds >> ev) & 1u) != 0u;
         const uint64_t m_fin = ballot(fin);
         if (m_fin) {
             const uint64_t in_c = ballot(fin && L.slot == cp);
