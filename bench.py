@@ -401,14 +401,35 @@ def main() -> int:
             per *= 4
         n_each = max(per, int(per * args.cpu_seconds / max(cal, 1e-6)))
         t0 = time.perf_counter()
+        coll = 0
         for s in specs:
-            run_oracle(s, histories=n_each, seed=s.seed + 11)
+            coll += run_oracle(s, histories=n_each, seed=s.seed + 11).collisions
         tc = time.perf_counter() - t0
+        # one thread on a sample a tenth of the size (histories are independent,
+        # so rates extrapolate linearly)
+        n_one = max(1000, n_each // (10 * max(1, oracle.max_threads())))
+        t1 = time.perf_counter()
+        for s in specs:
+            run_oracle(s, histories=n_one, seed=s.seed + 13, threads=1)
+        t1 = time.perf_counter() - t1
+        cpu_model = ""
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
         cpu = {"value": n_each * len(specs) / tc, "unit": "histories/s", "cores": oracle.max_threads(),
                "kind": "oracle",
                "sample": f"the {len(specs)} {args.workload} parameter sets x {n_each} histories each "
-                         f"({tc:.1f} s, FP64, OpenMP over 4096-history chunks)"}
-        log(f"cpu oracle: {cpu['value']:.4g} hist/s on {cpu['cores']} threads")
+                         f"({tc:.1f} s, FP64, OpenMP over 4096-history chunks)",
+               "collisions_per_s": coll / tc,
+               "single_thread_value": n_one * len(specs) / t1,
+               "single_thread_sample": f"{len(specs)} sets x {n_one} histories ({t1:.1f} s, 1 thread)",
+               "cpu_model": cpu_model, "logical_cpus": os.cpu_count()}
+        log(f"cpu oracle: {cpu['value']:.4g} hist/s on {cpu['cores']} threads "
+            f"({cpu['single_thread_value']:.4g} on 1 thread; {cpu_model})")
 
     traffic = measured_traffic() if args.workload == "cube3d_track" and not args.histories else None
     line = {
