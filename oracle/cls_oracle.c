@@ -432,3 +432,271 @@ int orc_run(const orc_problem *p, uint64_t seed, uint64_t h0, uint64_t n, int nt
     free(scores);
     return 0;
 }
+
+/* ======================================================================== */
+/* Quenched disorder in d = 1 (Section 3): reference solutions               */
+/* ======================================================================== */
+/*
+ * Section 3 builds reference solutions by sampling realizations of the
+ * stochastic medium and transporting particles through each one with the
+ * geometry frozen, then averaging the observables over realizations. In
+ * d = 1 a realization is the Poisson process on the line (Sec. 3.1): points
+ * of density rho = 1/Lambda cut [0, L] into cells, and each cell is coloured
+ * with material 0 with probability p_0 (Sec. 3.2), where
+ *   1/Lambda = 1/Lambda_0 + 1/Lambda_1,   p_0 = Lambda_0 / (Lambda_0 + Lambda_1),
+ * so that the clusters of material i have mean chord Lambda_i. Transport in
+ * a realization is ordinary surface tracking: the distance to collision in
+ * the current layer's material against the distance to the layer's face.
+ * Per realization the observables are history means (Sec. 3.3); the
+ * ensemble average is their mean over realizations.
+ *
+ * Readings (listed in the design notes): cells are generated from x = 0 by
+ * exponential gaps (the Poisson process restricted to [0, L]); neighbouring
+ * cells of one material form one layer (the medium is the same, and the
+ * transport draws a fresh collision distance at every face); ties between
+ * the face and the collision go to the face.
+ */
+
+typedef struct {
+    double *b;          /* n + 1 bounds                    */
+    int *m;             /* n materials                     */
+    int n, cap;
+} orc_layers;
+
+static int layers_push(orc_layers *ly, double x, int mat)
+{
+    if (ly->n + 2 > ly->cap) {
+        int nc = ly->cap ? 2 * ly->cap : 64;
+        double *nb = (double *)realloc(ly->b, sizeof(double) * (size_t)nc);
+        if (!nb) return -1;
+        ly->b = nb;
+        int *nm = (int *)realloc(ly->m, sizeof(int) * (size_t)nc);
+        if (!nm) return -1;
+        ly->m = nm;
+        ly->cap = nc;
+    }
+    ly->b[ly->n] = x;
+    ly->m[ly->n] = mat;
+    ly->n++;
+    return 0;
+}
+
+/* Realization k: cell i has gap -ln(U_0)/rho and material 0 iff U_1 < p_0,
+ * from the block at counter (i, 3, lo32(k), hi32(k)). */
+static int make_layers(const orc_problem *p, uint64_t seed, uint64_t k, orc_layers *ly)
+{
+    const double rho = 1.0 / p->lambda[0] + 1.0 / p->lambda[1];
+    const double p0 = p->lambda[0] / (p->lambda[0] + p->lambda[1]);
+    double x = 0.0;
+    ly->n = 0;
+    for (uint32_t i = 0;; ++i) {
+        double U[5];
+        orc_step_uniforms(seed, k, i, 3, U);
+        int mat = (U[1] < p0) ? 0 : 1;
+        double end = x + (-log(U[0]) / rho);
+        if (ly->n == 0 || ly->m[ly->n - 1] != mat) {
+            if (layers_push(ly, x, mat) != 0) return -1;
+        }
+        if (end >= p->L) break;
+        x = end;
+    }
+    ly->b[ly->n] = p->L;
+    return ly->n;
+}
+
+static int valid_quenched(const orc_problem *p)
+{
+    return valid_problem(p) && (p->geom == ORC_ROD || p->geom == ORC_SLAB);
+}
+
+int orc_quenched_layers(const orc_problem *p, uint64_t seed, uint64_t k,
+                        double *bounds, int *mat, int cap)
+{
+    if (!valid_quenched(p) || !bounds || !mat || cap < 1) return -1;
+    orc_layers ly = { NULL, NULL, 0, 0 };
+    int n = make_layers(p, seed, k, &ly);
+    if (n > 0) {
+        int w = n < cap ? n : cap;
+        for (int i = 0; i < w; ++i) {
+            bounds[i] = ly.b[i];
+            mat[i] = ly.m[i];
+        }
+        if (n <= cap) bounds[n] = ly.b[n];
+    }
+    free(ly.b);
+    free(ly.m);
+    return n;
+}
+
+typedef struct {
+    uint64_t histories, transmitted, reflected, absorbed, capped;
+    uint64_t flights, collisions, scatters, crossings;
+} quenched_counts;
+
+/* One history of global index g through the layers of its realization. */
+static int run_quenched_history(const orc_problem *p, const orc_layers *ly, uint64_t seed, uint64_t g,
+                                history_scratch *hs, quenched_counts *cnt)
+{
+    const double L = p->L;
+    const uint64_t cap = p->max_steps ? p->max_steps : ORC_DEFAULT_CAP;
+    double U[5];
+    double x = 0.0, mu;
+    int layer = 0;
+
+    /* --- source (step 0): the same laws as the CLS source in d = 1 ------ */
+    orc_step_uniforms(seed, g, 0, 2, U);
+    if (p->source == ORC_SRC_FACE) {
+        mu = (p->geom == ORC_ROD) ? 1.0 : sqrt(U[1]);
+    } else {
+        x = L * U[1];
+        if (p->geom == ORC_ROD) mu = (U[2] < 0.5) ? 1.0 : -1.0;
+        else                    mu = 2.0 * U[2] - 1.0;
+        while (layer + 1 < ly->n && ly->b[layer + 1] <= x) ++layer;   /* x in [b_i, b_i+1) */
+    }
+    int m = ly->m[layer];
+
+    for (uint64_t step = 1;; ++step) {
+        if (step > cap) { cnt->capped++; return ORC_EV_CAP; }
+        orc_step_uniforms(seed, g, (uint32_t)step, 2, U);
+        hs->flights++;
+        cnt->flights++;
+        double lc = -log(U[0]) / p->sigma[m];
+        double face = (mu > 0.0) ? ly->b[layer + 1] : ly->b[layer];
+        double lb = (face - x) / mu;
+        double xa = x;
+        if (lb <= lc) {
+            /* reach the layer's face: leak through x = 0 or x = L, or enter
+             * the neighbouring layer */
+            x = face;
+            if (p->estimator == ORC_EST_TRACK) score_track(p, hs, xa, x, mu, lb);
+            if (mu > 0.0 && layer + 1 == ly->n) { cnt->transmitted++; return ORC_EV_LEAK_XHI; }
+            if (mu < 0.0 && layer == 0)         { cnt->reflected++;   return ORC_EV_LEAK_XLO; }
+            layer += (mu > 0.0) ? 1 : -1;
+            m = ly->m[layer];
+            cnt->crossings++;
+        } else {
+            x += lc * mu;
+            if (p->estimator == ORC_EST_TRACK) score_track(p, hs, xa, x, mu, lc);
+            cnt->collisions++;
+            if (p->estimator == ORC_EST_COLLISION) add_score(p, hs, bin_of(p, x), 1.0 / p->sigma[m]);
+            if (U[2] < p->c[m]) {
+                cnt->scatters++;
+                if (p->geom == ORC_ROD) mu = (U[3] < 0.5) ? 1.0 : -1.0;
+                else                    mu = 2.0 * U[3] - 1.0;
+            } else {
+                cnt->absorbed++;
+                return ORC_EV_ABSORB;
+            }
+        }
+    }
+}
+
+typedef struct {
+    quenched_counts cnt;
+    uint64_t layers;
+    double obs[5];      /* T, R, A, total flux, leakage: this realization's history means */
+    double *bin;        /* nbins: this realization's mean score per bin           */
+    int failed;
+} realization_partial;
+
+static void run_realization(const orc_problem *p, uint64_t seed, uint64_t k, uint64_t N,
+                            realization_partial *rp, double *score, orc_layers *ly)
+{
+    memset(&rp->cnt, 0, sizeof rp->cnt);
+    memset(rp->bin, 0, sizeof(double) * (size_t)p->nbins);
+    rp->failed = 0;
+    int n = make_layers(p, seed, k, ly);
+    if (n < 0) { rp->failed = 1; return; }
+    rp->layers = (uint64_t)n;
+    double total = 0.0;
+    for (uint64_t h = 0; h < N; ++h) {
+        history_scratch hs;
+        hs.score = score;
+        hs.kmin = p->nbins;
+        hs.kmax = -1;
+        hs.total = 0.0;
+        hs.hash = 0xCBF29CE484222325ull;
+        hs.flights = 0;
+        run_quenched_history(p, ly, seed, k * N + h, &hs, &rp->cnt);
+        rp->cnt.histories++;
+        for (int b = hs.kmin; b <= hs.kmax; ++b) {
+            rp->bin[b] += score[b];
+            score[b] = 0.0;
+        }
+        total += hs.total;
+    }
+    const double inv = 1.0 / (double)N;
+    rp->obs[0] = (double)rp->cnt.transmitted * inv;
+    rp->obs[1] = (double)rp->cnt.reflected * inv;
+    rp->obs[2] = (double)rp->cnt.absorbed * inv;
+    rp->obs[3] = total * inv;
+    rp->obs[4] = 0.5 * (rp->obs[0] + rp->obs[1]);
+    for (int b = 0; b < p->nbins; ++b) rp->bin[b] *= inv;
+}
+
+int orc_run_quenched(const orc_problem *p, uint64_t seed, uint64_t k0, uint64_t M, uint64_t N,
+                     int nthreads, orc_quenched *out, double *bin_sum, double *bin_sq)
+{
+    if (!valid_quenched(p) || !out || !bin_sum || !bin_sq || N == 0) return -1;
+    const int K = p->nbins;
+    int nt = nthreads > 0 ? nthreads : orc_max_threads();
+    memset(out, 0, sizeof *out);
+    memset(bin_sum, 0, sizeof(double) * (size_t)K);
+    memset(bin_sq, 0, sizeof(double) * (size_t)K);
+    if (M == 0) return 0;
+
+    /* Realizations run in parallel in groups; their partials are added in
+     * realization order, so the result does not depend on the thread count. */
+    const uint64_t group = (uint64_t)nt * 8u;
+    realization_partial *rps = (realization_partial *)calloc((size_t)group, sizeof *rps);
+    double *arena = (double *)calloc((size_t)group * (size_t)K, sizeof(double));
+    double *scores = (double *)calloc((size_t)nt * (size_t)K, sizeof(double));
+    orc_layers *lys = (orc_layers *)calloc((size_t)nt, sizeof *lys);
+    if (!rps || !arena || !scores || !lys) { free(rps); free(arena); free(scores); free(lys); return -1; }
+    for (uint64_t i = 0; i < group; ++i) rps[i].bin = arena + (size_t)i * (size_t)K;
+
+    int rc = 0;
+    for (uint64_t g0 = 0; g0 < M && rc == 0; g0 += group) {
+        uint64_t gn = (M - g0) < group ? (M - g0) : group;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#endif
+        for (long long ri = 0; ri < (long long)gn; ++ri) {
+            int tid = 0;
+#ifdef _OPENMP
+            tid = omp_get_thread_num();
+#endif
+            run_realization(p, seed, k0 + g0 + (uint64_t)ri, N, &rps[ri], scores + (size_t)tid * (size_t)K,
+                            &lys[tid]);
+        }
+        for (uint64_t ri = 0; ri < gn; ++ri) {
+            const realization_partial *rp = &rps[ri];
+            if (rp->failed) { rc = -1; break; }
+            out->realizations++;
+            out->histories += rp->cnt.histories;
+            out->transmitted += rp->cnt.transmitted;
+            out->reflected += rp->cnt.reflected;
+            out->absorbed += rp->cnt.absorbed;
+            out->capped += rp->cnt.capped;
+            out->flights += rp->cnt.flights;
+            out->collisions += rp->cnt.collisions;
+            out->scatters += rp->cnt.scatters;
+            out->crossings += rp->cnt.crossings;
+            out->layers += rp->layers;
+            for (int j = 0; j < 5; ++j) {
+                out->sum[j] += rp->obs[j];
+                out->sq[j] += rp->obs[j] * rp->obs[j];
+            }
+            for (int b = 0; b < K; ++b) {
+                bin_sum[b] += rp->bin[b];
+                bin_sq[b] += rp->bin[b] * rp->bin[b];
+            }
+        }
+    }
+    for (int t = 0; t < nt; ++t) { free(lys[t].b); free(lys[t].m); }
+    free(lys);
+    free(rps);
+    free(arena);
+    free(scores);
+    return rc;
+}

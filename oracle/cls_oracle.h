@@ -77,6 +77,44 @@ int orc_run(const orc_problem *p, uint64_t seed, uint64_t h0, uint64_t n, int nt
 /* Number of OpenMP threads orc_run uses for nthreads <= 0. */
 int orc_max_threads(void);
 
+/* ---------------------------------------------------------------------- */
+/* Quenched disorder in d = 1 (Section 3): reference solutions            */
+/* ---------------------------------------------------------------------- */
+/* A realization of the binary Markov slab (Sec. 3.1-3.2): the points of a
+ * Poisson process of density rho = 1/Lambda on the line, 1/Lambda =
+ * 1/Lambda_0 + 1/Lambda_1, cut [0, L] into cells, and each cell is given
+ * material 0 with probability p_0 = Lambda_0 / (Lambda_0 + Lambda_1), 1
+ * otherwise. Cell i of realization k spans a gap -ln(U_0)/rho and has
+ * material 0 iff U_1 < p_0, with U_0, U_1 the first two uniforms of the
+ * Philox block at counter (i, 3, lo32(k), hi32(k)) under the problem seed.
+ * Neighbouring cells of one material are merged into one layer.
+ * Writes at most cap layers: bounds[0..n] (bounds[0] = 0, bounds[n] = L) and
+ * mat[0..n-1]; returns n, or -1 on an invalid argument (a layer count above
+ * cap returns the count without writing beyond cap). */
+int orc_quenched_layers(const orc_problem *p, uint64_t seed, uint64_t k,
+                        double *bounds, int *mat, int cap);
+
+typedef struct {
+    uint64_t realizations, histories, transmitted, reflected, absorbed, capped;
+    uint64_t flights, collisions, scatters, crossings, layers;
+    /* Per-realization means of T, R, A, the total flux (track length per
+     * history) and the leakage (T + R)/2: sum over realizations, and sum of
+     * squares. */
+    double sum[5], sq[5];
+} orc_quenched;
+
+/* Run realizations k0 .. k0+M-1 of problem p (geom ORC_ROD or ORC_SLAB), each
+ * with N histories transported through its fixed layers (Sec. 3.3): history
+ * h of realization k is global history g = k N + h, and its event step j
+ * draws the Philox block at counter (j, 2, lo32(g), hi32(g)). Per
+ * realization, the observables are history means; bin_sum[b] and bin_sq[b]
+ * (nbins each) get the sum over realizations of the realization's mean flux
+ * score in bin b (collision or track length, not divided by the bin width)
+ * and of its square. Results are bitwise independent of nthreads. Returns
+ * 0, or -1 on an invalid argument. */
+int orc_run_quenched(const orc_problem *p, uint64_t seed, uint64_t k0, uint64_t M, uint64_t N,
+                     int nthreads, orc_quenched *out, double *bin_sum, double *bin_sq);
+
 #ifdef __cplusplus
 }
 #endif

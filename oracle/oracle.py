@@ -53,6 +53,13 @@ class _Counts(ctypes.Structure):
                [("score_sum", ctypes.c_double), ("score_sq", ctypes.c_double)]
 
 
+class _Quenched(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("realizations", "histories", "transmitted", "reflected", "absorbed", "capped",
+                 "flights", "collisions", "scatters", "crossings", "layers")] + \
+               [("sum", ctypes.c_double * 5), ("sq", ctypes.c_double * 5)]
+
+
 _lib = None
 
 
@@ -84,6 +91,13 @@ def _declare(lib):
                                       ctypes.c_uint32, ctypes.c_void_p]
     lib.orc_step_uniforms.restype = None
     lib.orc_max_threads.restype = ctypes.c_int
+    lib.orc_quenched_layers.argtypes = [ctypes.POINTER(_Problem), ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lib.orc_quenched_layers.restype = ctypes.c_int
+    lib.orc_run_quenched.argtypes = [ctypes.POINTER(_Problem), ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                     ctypes.POINTER(_Quenched), ctypes.c_void_p, ctypes.c_void_p]
+    lib.orc_run_quenched.restype = ctypes.c_int
 
 
 @dataclass
@@ -208,3 +222,101 @@ def run(problem: Problem, histories: int, seed: int, h0: int = 0, threads: int =
                   total_flux=tot, total_flux_sigma=stot, bin_sum=bsum, bin_sq=bsq,
                   score_sum=float(cnt.score_sum), score_sq=float(cnt.score_sq),
                   trace_hash=th, trace_len=tl)
+
+
+# ---------------------------------------------------------------------------
+# Quenched disorder in d = 1 (Section 3): ensemble averages over realizations
+# ---------------------------------------------------------------------------
+@dataclass
+class QuenchedResult:
+    """Ensemble averages over realizations (Sec. 3.3) of the per-realization
+    history means; each sigma is the standard error of the mean over the M
+    independent realizations (it contains both the spread of the geometries
+    and the transport noise of each realization)."""
+    realizations: int
+    histories: int
+    transmitted: int
+    reflected: int
+    absorbed: int
+    capped: int
+    flights: int
+    collisions: int
+    scatters: int
+    crossings: int
+    layers: int
+    T: float
+    R: float
+    A: float
+    total_flux: float
+    sigma_T: float
+    sigma_R: float
+    sigma_A: float
+    total_flux_sigma: float
+    Lk: float               # leakage <(T + R)/2> (Sec. 2, suite II)
+    sigma_Lk: float
+    sigma_G: tuple          # spread of the per-realization T, R, A, total flux, leakage
+    flux: np.ndarray
+    flux_sigma: np.ndarray
+    sums: tuple
+    sqs: tuple
+    bin_sum: np.ndarray
+    bin_sq: np.ndarray
+
+
+def _ensemble(s: float, q: float, m: int) -> tuple[float, float, float]:
+    """Mean, standard error of the mean and spread of m per-realization values."""
+    if m == 0:
+        return 0.0, 0.0, 0.0
+    mean = s / m
+    if m < 2:
+        return mean, 0.0, 0.0
+    var = max(q / m - mean * mean, 0.0) * m / (m - 1)
+    return mean, float(np.sqrt(var / m)), float(np.sqrt(var))
+
+
+def quenched_layers(problem: Problem, seed: int, k: int, cap: int = 1 << 16, lib=None):
+    """Layers of realization k: (bounds[n+1], materials[n])."""
+    lib = lib or _load()
+    b = np.zeros(cap + 1, dtype=np.float64)
+    m = np.zeros(cap, dtype=np.int32)
+    cp = problem._c()
+    n = lib.orc_quenched_layers(ctypes.byref(cp), seed, k, b.ctypes.data, m.ctypes.data, cap)
+    if n < 0:
+        raise ValueError("oracle rejected the problem")
+    if n > cap:
+        raise ValueError(f"realization has {n} layers, more than {cap}")
+    return b[:n + 1].copy(), m[:n].copy()
+
+
+def run_quenched(problem: Problem, realizations: int, histories: int, seed: int, k0: int = 0,
+                 threads: int = 0, lib=None) -> QuenchedResult:
+    """Realizations k0 .. k0+M-1 of the d = 1 Markov medium, N histories each."""
+    lib = lib or _load()
+    K = int(problem.nbins)
+    q = _Quenched()
+    bsum = np.zeros(K, dtype=np.float64)
+    bsq = np.zeros(K, dtype=np.float64)
+    cp = problem._c()
+    rc = lib.orc_run_quenched(ctypes.byref(cp), seed, k0, realizations, histories, threads,
+                              ctypes.byref(q), bsum.ctypes.data, bsq.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle rejected the quenched problem")
+    M = int(q.realizations)
+    obs = [_ensemble(q.sum[j], q.sq[j], M) for j in range(5)]
+    dx = problem.L / K
+    flux = np.zeros(K)
+    fsig = np.zeros(K)
+    for b in range(K):
+        mean, sig, _ = _ensemble(bsum[b], bsq[b], M)
+        flux[b] = mean / dx
+        fsig[b] = sig / dx
+    return QuenchedResult(
+        realizations=M, histories=int(q.histories), transmitted=int(q.transmitted),
+        reflected=int(q.reflected), absorbed=int(q.absorbed), capped=int(q.capped),
+        flights=int(q.flights), collisions=int(q.collisions), scatters=int(q.scatters),
+        crossings=int(q.crossings), layers=int(q.layers),
+        T=obs[0][0], R=obs[1][0], A=obs[2][0], total_flux=obs[3][0],
+        sigma_T=obs[0][1], sigma_R=obs[1][1], sigma_A=obs[2][1], total_flux_sigma=obs[3][1],
+        Lk=obs[4][0], sigma_Lk=obs[4][1],
+        sigma_G=tuple(o[2] for o in obs), flux=flux, flux_sigma=fsig,
+        sums=tuple(q.sum), sqs=tuple(q.sq), bin_sum=bsum, bin_sq=bsq)

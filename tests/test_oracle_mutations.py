@@ -71,6 +71,27 @@ def absorber_z(lib, geom, name):
     return abs(float(z(r.T, r.sigma_T, T, 0))), int(np.sum(np.abs(zb) > 4))
 
 
+def quenched_absorber_z(lib, geom, name):
+    """Quenched pure absorber (d = 1) against the exact Markov ensemble average."""
+    sigma, lam, L, K = (0.2, 2.0), (1.0, 0.3), 5.0, 20
+    r = o.run_quenched(P(geom=geom, sigma=sigma, c=(0, 0), lam=lam, nbins=K, L=L), 20000, 20, 4321, lib=lib)
+    T, _ = cf.markov_absorber(name, sigma, lam, L, K)
+    return abs(float(z(r.T, r.sigma_T, T, 0))) if r.capped == 0 else np.inf
+
+
+def quenched_paper_z(lib, suite, case):
+    """A d = 1 quenched reference row of Tables 3-8."""
+    from test_oracle_quenched import REF_ROWS
+    s = paper_case(case, 1, suite, histories=1)
+    r = o.run_quenched(P(geom=o.SLAB, sigma=s.sigma, c=s.c, lam=s.lam, nbins=100, source=s.source),
+                       10000, 100, 31, lib=lib)
+    row = next(v for (su, ca, dd, v, _) in REF_ROWS if (su, ca, dd) == (suite, case, 1))
+    obs = {"R": (r.R, r.sigma_R), "T": (r.T, r.sigma_T), "flux": (r.total_flux, r.total_flux_sigma),
+           "Lk": (r.Lk, r.sigma_Lk)}
+    zz = [abs(float(z(*obs[k], *row[k]))) for k in row]
+    return max(zz) if r.capped == 0 else np.inf
+
+
 def test_unmutated_oracle_passes_the_same_checks(mutant_dir):
     lib = build_mutant(mutant_dir, "identity", "#include <math.h>", "#include <math.h>")
     assert paper_row_z(lib, "I", "1a", 2) < 4
@@ -78,6 +99,9 @@ def test_unmutated_oracle_passes_the_same_checks(mutant_dir):
     assert zr < 4 and nb <= allowed_beyond_4(50)
     zt, nb = absorber_z(lib, o.EXT2D, "ext2d")
     assert zt < 4 and nb <= allowed_beyond_4(20)
+    assert quenched_absorber_z(lib, o.SLAB, "slab") < 4
+    assert quenched_paper_z(lib, "II", "1a") < 4
+    assert quenched_paper_z(lib, "I", "2c") < 4
 
 
 MUTATIONS = {
@@ -119,6 +143,20 @@ MUTATIONS = {
     "distance_to_face_sign": ("else if (u[a] < 0.0) { d = (0.0 - x[a]) / u[a]; f = 2 * a; }",
                               "else if (u[a] < 0.0) { d = (L - x[a]) / -u[a]; f = 2 * a; }",
                               lambda lib: rod_lp_z(lib)[0] > 4),
+    # quenched realizations (Section 3)
+    "quenched_density_of_one_material": ("const double rho = 1.0 / p->lambda[0] + 1.0 / p->lambda[1];",
+                                         "const double rho = 1.0 / p->lambda[0];",
+                                         lambda lib: quenched_absorber_z(lib, o.SLAB, "slab") > 4),
+    "quenched_colour_unweighted": ("int mat = (U[1] < p0) ? 0 : 1;", "int mat = (U[1] < 0.5) ? 0 : 1;",
+                                   lambda lib: quenched_absorber_z(lib, o.ROD, "rod") > 4),
+    "quenched_source_layer_not_located": ("while (layer + 1 < ly->n && ly->b[layer + 1] <= x) ++layer;",
+                                          "(void)0;",
+                                          lambda lib: quenched_paper_z(lib, "II", "1a") > 4),
+    "quenched_material_kept_at_face": ("            m = ly->m[layer];\n            cnt->crossings++;",
+                                       "            cnt->crossings++;",
+                                       lambda lib: quenched_absorber_z(lib, o.SLAB, "slab") > 4),
+    "quenched_face_distance_unsigned": ("double lb = (face - x) / mu;", "double lb = (face - x) / fabs(mu);",
+                                        lambda lib: quenched_paper_z(lib, "I", "2c") > 4),
 }
 
 
