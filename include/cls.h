@@ -48,7 +48,8 @@ typedef enum {
     CLS_ERR_NOT_READY = 4,     /* asynchronous work is still running            */
     CLS_ERR_EVENT_CAP = 5,     /* a history hit the per-history flight cap      */
     CLS_ERR_STATE = 6,         /* call out of order (e.g. read before any run)  */
-    CLS_ERR_NO_DEVICE = 7      /* no usable gfx950 device                       */
+    CLS_ERR_NO_DEVICE = 7,     /* no usable gfx950 device                       */
+    CLS_ERR_CAPACITY = 8       /* a quenched realization exceeded the layer capacity */
 } cls_status;
 
 /* Source (Section 2): suite I = normalized incident angular flux on x = 0
@@ -262,6 +263,57 @@ cls_status cls_server_release(cls_server *s, uint64_t ticket);
 cls_status cls_server_get_stats(cls_server *s, cls_server_stats *out);
 /* Finish all submitted work, then stop the worker and free the server. */
 void cls_server_destroy(cls_server *s);
+
+/* ---------------------------------------------------------------------- */
+/* Quenched-disorder reference solutions, d = 1 (Section 3)               */
+/* ---------------------------------------------------------------------- */
+/* Reference solutions average each observable over realizations of the
+ * stochastic medium transported with their geometry frozen (Sec. 3.3). For a
+ * d = 1 problem (the rod, or the slab with CLS_F_D1_SLAB), realization k is
+ * the Poisson process on the line (Sec. 3.1) of density
+ * rho = 1/Lambda_0 + 1/Lambda_1 cutting [0, L] into cells, each of material 0
+ * with probability p_0 = Lambda_0 / (Lambda_0 + Lambda_1) (Sec. 3.2); cell i
+ * draws its gap -ln(U_0)/rho and its material (U_1 < p_0) from the Philox
+ * block (i, 3, lo32(k), hi32(k)) under `seed`, and neighbouring cells of one
+ * material form one layer. Each realization transports `histories` histories
+ * (history h of realization k is global history g = k * histories + h; its
+ * event step j draws the block (j, 2, lo32(g), hi32(g))) with the problem's
+ * source, materials and flux estimator; the observables of a realization
+ * are its history means, and the results are their means over the
+ * `realizations` realizations with the standard error of each mean.
+ *
+ * cls_run_quenched: synchronous; runs on the problem's stream (cls_set_stream)
+ * or the default stream, allocating a small workspace with the problem on the
+ * first call. Tracking is FP64 (CLS_F_FP32 and CLS_F_TRACE are rejected).
+ * Errors: CLS_ERR_INVALID_ARG (d != 1, FP32 or trace problem, zero counts,
+ * realizations x histories >= 2^62, a medium whose expected layer count
+ * 1 + 2L/(Lambda_0 + Lambda_1) exceeds 1024 or whose expected cell count
+ * rho L exceeds 10^6); CLS_ERR_CAPACITY if a realization had more layers than the
+ * workspace holds (its results are then not valid); CLS_ERR_EVENT_CAP if a
+ * history reached the flight cap; CLS_ERR_NO_DEVICE; CLS_ERR_DEVICE;
+ * CLS_ERR_OUT_OF_MEMORY. */
+cls_status cls_run_quenched(cls_problem *p, uint64_t realizations, uint64_t histories, uint64_t seed);
+
+/* Results of the last cls_run_quenched. mean_* are ensemble means of the
+ * per-realization history means; sigma_* the standard errors of those means
+ * over the independent realizations (geometric spread and transport noise
+ * together); spread_* the standard deviation of the per-realization values
+ * (the sigma_G of Sec. 3.3). Lk is the leakage (T + R)/2 (suite II). */
+typedef struct {
+    uint64_t realizations, histories, transmitted, reflected, absorbed, capped;
+    uint64_t flights, collisions, scatters, crossings, layers;
+    double T, R, A, total_flux, Lk;
+    double sigma_T, sigma_R, sigma_A, sigma_total_flux, sigma_Lk;
+    double spread_T, spread_R, spread_A, spread_total_flux, spread_Lk;
+    double track_ms;               /* GPU time of the transport kernel */
+} cls_quenched_tallies;
+
+/* Copies the last quenched results; flux and flux_sigma (caller-owned, nbins
+ * doubles each, may be NULL) get the ensemble-mean scalar flux per bin and its
+ * standard error. Errors: CLS_ERR_INVALID_ARG (NULL out, nbins differing from
+ * the problem's when flux is given), CLS_ERR_STATE (no quenched run yet). */
+cls_status cls_read_quenched(const cls_problem *p, cls_quenched_tallies *out, double *flux, double *flux_sigma,
+                             int nbins);
 
 /* Status name and the calling thread's last error detail. */
 const char *cls_status_string(cls_status s);

@@ -32,6 +32,7 @@ CLS_ERR_NOT_READY = 4
 CLS_ERR_EVENT_CAP = 5
 CLS_ERR_STATE = 6
 CLS_ERR_NO_DEVICE = 7
+CLS_ERR_CAPACITY = 8
 
 CLS_SRC_FACE_X0 = 0
 CLS_SRC_VOLUME = 1
@@ -52,6 +53,7 @@ EXPORTED = (
     "cls_set_launch_config", "cls_get_launch_config", "cls_autotune",
     "cls_server_create", "cls_server_submit", "cls_server_poll", "cls_server_wait",
     "cls_server_request_info", "cls_server_release", "cls_server_get_stats", "cls_server_destroy",
+    "cls_run_quenched", "cls_read_quenched",
     "cls_status_string", "cls_last_error", "cls_version",
 )
 
@@ -63,6 +65,16 @@ class cls_tallies(ctypes.Structure):
         [(n, ctypes.c_double) for n in (
             "T", "R", "A", "sigma_T", "sigma_R", "sigma_A", "total_flux", "sigma_total_flux",
             "track_ms")]
+
+
+class cls_quenched_tallies(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "realizations", "histories", "transmitted", "reflected", "absorbed", "capped", "flights",
+        "collisions", "scatters", "crossings", "layers")] + \
+        [(n, ctypes.c_double) for n in (
+            "T", "R", "A", "total_flux", "Lk",
+            "sigma_T", "sigma_R", "sigma_A", "sigma_total_flux", "sigma_Lk",
+            "spread_T", "spread_R", "spread_A", "spread_total_flux", "spread_Lk", "track_ms")]
 
 
 class cls_launch_config(ctypes.Structure):
@@ -129,6 +141,8 @@ _sig("cls_server_get_stats", ctypes.c_int, _P, ctypes.POINTER(cls_server_stats))
 _sig("cls_server_destroy", None, _P)
 _sig("cls_set_launch_config", ctypes.c_int, ctypes.POINTER(cls_launch_config))
 _sig("cls_get_launch_config", ctypes.c_int, ctypes.POINTER(cls_launch_config))
+_sig("cls_run_quenched", ctypes.c_int, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64)
+_sig("cls_read_quenched", ctypes.c_int, _P, ctypes.POINTER(cls_quenched_tallies), _P, _P, ctypes.c_int)
 _sig("cls_status_string", ctypes.c_char_p, ctypes.c_int)
 _sig("cls_last_error", ctypes.c_char_p)
 _sig("cls_version", ctypes.c_char_p)
@@ -335,6 +349,22 @@ def cls_server_get_stats(s: int) -> dict:
 
 def cls_server_destroy(s: int) -> None:
     _lib.cls_server_destroy(s)
+
+
+def cls_run_quenched(p: int, realizations: int, histories: int, seed: int) -> None:
+    """Quenched-disorder reference solution of a d = 1 problem (synchronous)."""
+    _check(_lib.cls_run_quenched(p, int(realizations), int(histories), int(seed) & (2**64 - 1)),
+           "cls_run_quenched")
+
+
+def cls_read_quenched(p: int, nbins: int):
+    """Returns (cls_quenched_tallies, flux[nbins], flux_sigma[nbins])."""
+    t = cls_quenched_tallies()
+    flux = np.zeros(nbins, dtype=np.float64)
+    fsig = np.zeros(nbins, dtype=np.float64)
+    _check(_lib.cls_read_quenched(p, ctypes.byref(t), flux.ctypes.data, fsig.ctypes.data, int(nbins)),
+           "cls_read_quenched")
+    return t, flux, fsig
 
 
 def cls_status_string(status: int) -> str:

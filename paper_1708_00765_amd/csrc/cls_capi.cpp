@@ -311,6 +311,7 @@ const char *cls_status_string(cls_status s)
     case CLS_ERR_EVENT_CAP: return "CLS_ERR_EVENT_CAP";
     case CLS_ERR_STATE: return "CLS_ERR_STATE";
     case CLS_ERR_NO_DEVICE: return "CLS_ERR_NO_DEVICE";
+    case CLS_ERR_CAPACITY: return "CLS_ERR_CAPACITY";
     }
     return "CLS_ERR_UNKNOWN";
 }
@@ -367,6 +368,7 @@ void cls_destroy_problem(cls_problem *p)
 {
     if (!p) return;
     release_device(p);
+    quenched_release(p);
     if (p->h_prob) (void)hipHostFree(p->h_prob);
     if (p->h_items) (void)hipHostFree(p->h_items);
     if (p->h_record) (void)hipHostFree(p->h_record);

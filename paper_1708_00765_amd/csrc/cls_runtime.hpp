@@ -11,6 +11,8 @@
 #include "cls.h"
 #include "cls_internal.hpp"
 
+struct QuenchedState;   // quenched-disorder workspace (cls_quenched_api.cpp)
+
 // ---------------------------------------------------------------------------
 // problem object
 // ---------------------------------------------------------------------------
@@ -45,6 +47,8 @@ struct cls_problem {
     bool timed_by_events = false;   // track_ms comes from ev_k0/ev_k1
     float track_ms = 0.0f;
     uint64_t histories = 0, seed = 0, trace_n = 0;
+    // quenched-disorder runs (d = 1), allocated on first use
+    QuenchedState *quenched = nullptr;
 };
 
 
@@ -79,6 +83,7 @@ Variant variant_of(const cls_problem *p);
 bool same_variant(const Variant &a, const Variant &b);
 cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
                      size_t *lds, int *lds_stride, LaunchShape *used);
+void quenched_release(cls_problem *p);
 
 }  // namespace rt
 }  // namespace cls

@@ -26,7 +26,7 @@ def cls():
 
 def test_every_declared_function_is_exported(cls):
     names = declared_functions()
-    assert len(names) >= 31
+    assert len(names) >= 33
     for n in names:
         assert hasattr(cls._lib, n), n
     assert set(names) == set(cls.EXPORTED)
@@ -138,3 +138,25 @@ def test_batch_argument_validation(cls):
     finally:
         cls.cls_destroy_problem(a)
         cls.cls_destroy_problem(b)
+
+
+def test_quenched_arguments_and_device(cls):
+    slab = cls.cls_create_problem(1, 10.0, (0.5, 1.0), (0.2, 0.9), (1.0, 0.3), flags=cls.CLS_F_D1_SLAB)
+    cube = cls.cls_create_problem(3, 10.0, (0.5, 1.0), (0.2, 0.9), (1.0, 0.3))
+    f32 = cls.cls_create_problem(1, 10.0, (0.5, 1.0), (0.2, 0.9), (1.0, 0.3), flags=cls.CLS_F_FP32)
+    fine = cls.cls_create_problem(1, 10.0, (0.5, 1.0), (0.2, 0.9), (0.005, 0.005))   # ~2000 layers expected
+    try:
+        for p, m, n in ((cube, 10, 10), (f32, 10, 10), (slab, 0, 10), (slab, 10, 0), (fine, 10, 10)):
+            with pytest.raises(cls.ClsError) as ei:
+                cls.cls_run_quenched(p, m, n, 1)
+            assert ei.value.status == cls.CLS_ERR_INVALID_ARG
+        with pytest.raises(cls.ClsError) as ei:            # nothing to read yet
+            cls.cls_read_quenched(slab, 100)
+        assert ei.value.status == cls.CLS_ERR_STATE
+        with pytest.raises(cls.ClsError) as ei:            # valid arguments, no GPU here
+            cls.cls_run_quenched(slab, 10, 10, 1)
+        assert ei.value.status == cls.CLS_ERR_NO_DEVICE
+        assert cls.cls_status_string(cls.CLS_ERR_CAPACITY) == "CLS_ERR_CAPACITY"
+    finally:
+        for p in (slab, cube, f32, fine):
+            cls.cls_destroy_problem(p)
