@@ -173,6 +173,87 @@ def run_paper_rows(cls, torch, stream, histories, fp32):
     return out
 
 
+def paper_realizations(suite, case):
+    """Realizations per d = 1 reference row (Sec. 3.3): 4e4 for sub-cases 1b,
+    5e4 for 2b, 1e5 for 3b, 5e4 for suite II 2a, 1e4 otherwise."""
+    if case == "1b":
+        return 40_000
+    if case == "2b" or (suite == "II" and case == "2a"):
+        return 50_000
+    if case == "3b":
+        return 100_000
+    return 10_000
+
+
+def load_paper_ref_rows():
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_ref_rows.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "I":
+            vals = {"R": (float(f[3]), float(f[4])), "T": (float(f[5]), float(f[6])),
+                    "flux": (float(f[7]), float(f[8]))}
+            t_tot = float(f[9])
+        else:
+            vals = {"Lk": (float(f[3]), float(f[4])), "flux": (float(f[5]), float(f[6]))}
+            t_tot = float(f[7])
+        rows.append((f[0], f[1], int(f[2]), vals, t_tot, f[-1]))
+    return rows
+
+
+def run_paper_ref_rows(cls, torch, stream, histories, cls_histories):
+    """The d = 1 quenched reference rows of Tables 3-8 on the GPU: the paper's
+    ensemble size per row (Sec. 3.3) with `histories` histories per
+    realization, against the printed Ref values; and, with cls_histories > 0,
+    the CLS error (CLS - Ref) / Ref of this GPU's own CLS and reference runs
+    against the paper's CLS and Ref rows."""
+    import math
+    from paper_1708_00765_amd.inputs import paper_case
+    cls_rows = {(r[0], r[1], r[2]): r[3] for r in load_paper_rows()}
+    out = []
+    for i, (suite, case, d, vals, t_tot, table) in enumerate(load_paper_ref_rows()):
+        if d != 1:
+            continue
+        s = paper_case(case, 1, suite, histories=1, seed=990000 + i)
+        p = make_problem(cls, s, False)
+        cls.cls_set_stream(p, stream)
+        M = paper_realizations(suite, case)
+        cls.cls_run_quenched(p, 10, 10, s.seed + 1)                # warm the code object
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cls.cls_run_quenched(p, M, histories, s.seed)
+        g, _, _ = cls.cls_read_quenched(p, s.nbins)
+        wall = time.perf_counter() - t0
+        cls.cls_destroy_problem(p)
+        obs = {"R": (g.R, g.sigma_R), "T": (g.T, g.sigma_T), "flux": (g.total_flux, g.sigma_total_flux),
+               "Lk": (g.Lk, g.sigma_Lk)}
+        zs = {k: (obs[k][0] - v) / math.hypot(obs[k][1], sv) for k, (v, sv) in vals.items()}
+        row = {"table": table, "suite": suite, "case": case, "d": 1, "realizations": M,
+               "histories_per_realization": histories, "ours": {k: obs[k][0] for k in vals},
+               "ours_sigma": {k: obs[k][1] for k in vals}, "paper": {k: vals[k][0] for k in vals}, "z": zs,
+               "gpu_s": wall, "paper_t_tot_s": t_tot}
+        if cls_histories > 0:
+            c = paper_case(case, 1, suite, histories=cls_histories, seed=991000 + i)
+            pc = make_problem(cls, c, True)
+            cls.cls_set_stream(pc, stream)
+            cls.cls_run(pc, cls_histories, c.seed)
+            t, _, _ = cls.cls_read_tallies(pc, c.nbins)
+            cls.cls_destroy_problem(pc)
+            n = t.histories
+            cobs = {"R": t.R, "T": t.T, "flux": t.total_flux, "Lk": 0.5 * (t.transmitted + t.reflected) / n}
+            pcls = cls_rows[(suite, case, 1)]
+            row["cls_error_pct"] = {k: 100.0 * (cobs[k] - obs[k][0]) / obs[k][0] for k in vals}
+            row["paper_cls_error_pct"] = {k: 100.0 * (pcls[k][0] - vals[k][0]) / vals[k][0] for k in vals}
+        out.append(row)
+        msg = ", ".join(f"{k} z={zs[k]:+.2f}" for k in zs)
+        if cls_histories > 0:
+            msg += "; CLS error " + ", ".join(f"{k} {row['cls_error_pct'][k]:+.2f}% (paper "
+                                              f"{row['paper_cls_error_pct'][k]:+.2f}%)" for k in zs)
+        log(f"  {table} {suite:2s} {case} d=1 Ref, M={M}: {msg}; {wall:.2f} s (paper t_tot {t_tot:.3g} s)")
+    return out
+
+
 def run_ext2d_comparison(cls, torch, stream, steps):
     """The 256 uneven ext2d sets (1e4..1e7 histories, 100..1000 bins): one batched
     FP32 persistent launch per pass vs one plain FP64 launch per set."""
@@ -267,6 +348,11 @@ def main() -> int:
     ap.add_argument("--paper-rows", type=float, default=0,
                     help="histories per row for the 54 CLS rows of Tables 3-8 (0 = skip; the paper used 1e9)")
     ap.add_argument("--paper-precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--paper-ref-rows", type=float, default=0,
+                    help="histories per realization for the 18 d = 1 quenched reference rows of Tables 3-8 "
+                         "(0 = skip; the paper used 1e6), at the paper's realization counts")
+    ap.add_argument("--paper-ref-cls", type=float, default=1e9,
+                    help="histories of the CLS run compared with each reference row (0 = skip)")
     ap.add_argument("--paper-out", default="", help="write the per-row results of --paper-rows to this JSON file")
     args = ap.parse_args()
 
@@ -383,6 +469,25 @@ def main() -> int:
             with open(args.paper_out, "w") as f:
                 json.dump({"summary": paper, "rows": rows}, f, indent=1)
 
+    # ---- the paper's d = 1 quenched reference rows ------------------------------
+    paper_ref = None
+    if args.paper_ref_rows > 0:
+        log(f"paper reference rows: 18 d = 1 Ref rows of Tables 3-8, {args.paper_ref_rows:.3g} histories "
+            f"per realization, FP64")
+        rows = run_paper_ref_rows(cls, torch, stream, int(args.paper_ref_rows), int(args.paper_ref_cls))
+        zmax = max(abs(v) for r in rows for v in r["z"].values())
+        paper_ref = {"rows": len(rows), "histories_per_realization": int(args.paper_ref_rows),
+                     "max_abs_z": zmax,
+                     "beyond_4_sigma": sum(1 for r in rows for v in r["z"].values() if abs(v) >= 4),
+                     "gpu_seconds": sum(r["gpu_s"] for r in rows),
+                     "paper_t_tot_seconds": sum(r["paper_t_tot_s"] for r in rows)}
+        log(f"paper reference rows: max |z| {zmax:.2f}, {paper_ref['beyond_4_sigma']} beyond 4 sigma, GPU "
+            f"{paper_ref['gpu_seconds']:.1f} s vs paper t_tot {paper_ref['paper_t_tot_seconds']:.3g} s")
+        if args.paper_out:
+            base, ext = os.path.splitext(args.paper_out)
+            with open(base + "_ref" + (ext or ".json"), "w") as f:
+                json.dump({"summary": paper_ref, "rows": rows}, f, indent=1)
+
     # ---- CPU oracle on a bounded sample ---------------------------------------
     cpu = None
     if args.cpu_seconds > 0:
@@ -464,6 +569,7 @@ def main() -> int:
         "served": served,
         "ext2d_batched_vs_fp64_plain": ext2d,
         "paper_rows": paper,
+        "paper_reference_rows": paper_ref,
     }
     print(json.dumps(line), flush=True)
     return 0
