@@ -61,6 +61,8 @@ constexpr int kDefaultMaxChunk = 16384;
 constexpr uint64_t kDefaultMaxSteps = 100000000ull;
 constexpr size_t kLdsLimit = 65536;
 constexpr int kDefaultRefillMin = 4;
+// smallest chunk (histories) for which one LDS tally buffer per wave pays
+constexpr uint64_t kSingleSlotMinChunk = 2048;
 }  // namespace
 
 namespace cls {
@@ -243,33 +245,48 @@ Variant variant_of(const cls_problem *p)
     return v;
 }
 
-// Launch shape. Each wave needs two LDS tally buffers; a workgroup uses at
-// most kLdsLimit. Unless the caller fixed them, the workgroup size (1, 2, 4 or
-// 8 waves) is the one that keeps the most waves resident per compute unit
-// (occupancy query; ties go to 4, then 8, 2 and 1 waves: 4-wave workgroups
-// measured fastest at equal residency) and the persistent grid holds
-// as many workgroups as the compute units keep resident at once.
+// Launch shape. Each wave needs one or two LDS tally buffers (two let a
+// wave start its next chunk while the last histories of the previous one
+// finish; one halves the LDS, at the cost of waiting for those histories,
+// which only pays with chunks of several thousand histories);
+// a workgroup uses at most kLdsLimit. Unless the caller fixed them, the
+// workgroup size (1, 2, 4 or 8 waves) and the buffer count are the ones
+// that keep the most waves resident per compute unit (occupancy query; ties
+// go to two buffers, and to 4, then 8, 2 and 1 waves: 4-wave workgroups
+// measured fastest at equal residency) and the persistent grid holds as
+// many workgroups as the compute units keep resident at once.
 cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
-                     size_t *lds, int *lds_stride, LaunchShape *used)
+                     size_t *lds, int *lds_stride, LaunchShape *used, uint64_t min_histories)
 {
     LaunchShape s = current_shape();
     int kp = max_bins + 1;
     kp += kp & 1;
-    const size_t per_wave = (2u * (size_t)kp + kWaveExtraDoubles) * sizeof(double);
     const size_t limit = std::min(kLdsLimit, di.lds_per_block ? di.lds_per_block : kLdsLimit);
-    if (per_wave > limit) return fail(CLS_ERR_INVALID_ARG, "flux mesh too large for LDS");
-    int best_waves = 0, best_bpc = 0;
+    auto wave_bytes = [&](int slots) { return ((size_t)slots * (size_t)kp + kWaveExtraDoubles) * sizeof(double); };
+    if (wave_bytes(1) > limit) return fail(CLS_ERR_INVALID_ARG, "flux mesh too large for LDS");
+    int best_waves = 0, best_bpc = 0, best_slots = 2;
     const int candidates[4] = {4, 8, 2, 1};
-    for (int c : candidates) {
-        if (s.waves_per_block > 0 && c != s.waves_per_block) continue;
-        if (per_wave * (size_t)c > limit) continue;
-        int bpc = s.blocks_per_cu;
-        if (bpc <= 0) {
-            const hipError_t e = track_occupancy(v, c * 64, per_wave * (size_t)c, &bpc);
-            if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    for (int slots = 2; slots >= 1; --slots) {
+        const size_t pw = wave_bytes(slots);
+        for (int c : candidates) {
+            if (s.waves_per_block > 0 && c != s.waves_per_block) continue;
+            if (pw * (size_t)c > limit) continue;
+            int bpc = s.blocks_per_cu;
+            if (bpc <= 0) {
+                const hipError_t e = track_occupancy(v, c * 64, pw * (size_t)c, &bpc);
+                if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+            }
+            if (slots == 1) {
+                const uint64_t waves_total = (uint64_t)di.cus * (uint64_t)std::max(bpc, 1) * (uint64_t)c;
+                if (min_histories == 0 ||
+                    chunk_size(min_histories, waves_total, (uint64_t)s.max_chunk) < kSingleSlotMinChunk)
+                    continue;
+            }
+            if (bpc * c > best_bpc * best_waves) { best_waves = c; best_bpc = bpc; best_slots = slots; }
         }
-        if (bpc * c > best_bpc * best_waves) { best_waves = c; best_bpc = bpc; }
     }
+    const size_t per_wave = wave_bytes(best_waves ? best_slots : 1);
+    if (best_waves == 0) best_slots = 1;
     if (best_waves == 0) {   // a fixed workgroup size that does not fit: shrink it
         best_waves = s.waves_per_block;
         while (best_waves > 1 && per_wave * (size_t)best_waves > limit) --best_waves;
@@ -286,6 +303,7 @@ cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *
     *grid = di.cus * best_bpc;
     s.waves_per_block = best_waves;
     s.blocks_per_cu = best_bpc;
+    s.slots = best_slots;
     *used = s;
     return CLS_OK;
 }
@@ -470,7 +488,7 @@ cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed)
     int grid, block, stride;
     size_t lds;
     LaunchShape used;
-    st = shape_for(variant_of(p), p->nbins, di, &grid, &block, &lds, &stride, &used);
+    st = shape_for(variant_of(p), p->nbins, di, &grid, &block, &lds, &stride, &used, histories);
     if (st != CLS_OK) return st;
     const uint64_t waves_total = (uint64_t)grid * (uint64_t)(block / 64);
     const uint64_t chunk = chunk_size(histories, waves_total, (uint64_t)used.max_chunk);
@@ -491,6 +509,7 @@ cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed)
     a.nprobs = 1;
     a.lds_stride = stride;
     a.refill_min = used.refill_min;
+    a.slots = used.slots;
     HIP_TRY(hipEventRecord(p->ev_k0, s));
     HIP_TRY(launch_track(variant_of(p), a, grid, block, lds, s));
     HIP_TRY(hipEventRecord(p->ev_k1, s));
@@ -653,8 +672,10 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     std::lock_guard<std::mutex> lk(g_batch_mu);
     int max_bins = 1;
     size_t rec_words = 0;
+    uint64_t min_hist = histories[0];
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
+        min_hist = std::min(min_hist, histories[i]);
         const uint64_t tn = trace_count(p, histories[i]);
         cls_status st = ensure_device(p, tn);
         if (st != CLS_OK) return st;
@@ -669,7 +690,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     int grid, block, stride;
     size_t lds;
     LaunchShape used;
-    st = shape_for(variant_of(problems[0]), max_bins, di, &grid, &block, &lds, &stride, &used);
+    st = shape_for(variant_of(problems[0]), max_bins, di, &grid, &block, &lds, &stride, &used, min_hist);
     if (st != CLS_OK) return st;
     const size_t probs_bytes = align256((size_t)n * sizeof(DevProblem));
     const size_t items_bytes = align256(((size_t)n + 2) * sizeof(uint64_t));
@@ -706,6 +727,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     a.nprobs = n;
     a.lds_stride = stride;
     a.refill_min = used.refill_min;
+    a.slots = used.slots;
     HIP_TRY(hipEventRecord(bs->k0, s));
     HIP_TRY(launch_track(variant_of(problems[0]), a, grid, block, lds, s));
     HIP_TRY(hipEventRecord(bs->k1, s));

@@ -24,7 +24,7 @@ struct cls_batch {
     char *dev = nullptr;
     char *host = nullptr;
     size_t probs_bytes = 0, items_bytes = 0, rec_words = 0;
-    int grid = 0, block = 0, stride = 0, refill_min = 1;
+    int grid = 0, block = 0, stride = 0, refill_min = 1, slots = 2;
     size_t lds = 0;
     uint64_t max_chunk = 0, waves_total = 0;
     hipGraph_t graph = nullptr;
@@ -60,6 +60,7 @@ static cls_status capture(cls_batch *b)
     a.nprobs = n;
     a.lds_stride = b->stride;
     a.refill_min = b->refill_min;
+    a.slots = b->slots;
     HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipMemcpyAsync(b->dev, b->host, b->probs_bytes + b->items_bytes, hipMemcpyHostToDevice,
                                   b->stream);
@@ -114,6 +115,7 @@ cls_status cls_batch_create(cls_problem *const *problems, int n, cls_batch **out
     st = shape_for(b->v, max_bins, di, &b->grid, &b->block, &b->lds, &b->stride, &used);
     if (st != CLS_OK) { batch_release(b); delete b; return st; }
     b->refill_min = used.refill_min;
+    b->slots = used.slots;
     b->max_chunk = (uint64_t)used.max_chunk;
     b->waves_total = (uint64_t)b->grid * (uint64_t)(b->block / 64);
     b->probs_bytes = align256((size_t)n * sizeof(DevProblem));

@@ -73,6 +73,7 @@ struct TrackArgs {
     int nprobs;
     int lds_stride;              // doubles per tally buffer (>= max nbins + 1, even)
     int refill_min;              // idle lanes a wave waits for before handing out histories
+    int slots;                   // LDS tally buffers per wave: 2, or 1 for large meshes
 };
 
 // LDS per wave beyond its two tally buffers: score sums of the two slots
@@ -88,6 +89,7 @@ struct LaunchShape {
     int blocks_per_cu;
     int max_chunk;
     int refill_min;
+    int slots = 2;               // chosen by the launch sizing, not by the caller
 };
 
 // Kernel variants: geometry x estimator x source x precision x trace.

@@ -81,8 +81,12 @@ void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, u
                       uint64_t trace_n, DevProblem *out);
 Variant variant_of(const cls_problem *p);
 bool same_variant(const Variant &a, const Variant &b);
+// min_histories: the smallest history count among the launch's problems, or
+// 0 when it is not known (graph batches, the server): one tally buffer per
+// wave is considered only when that problem's chunks would hold at least
+// kSingleSlotMinChunk histories.
 cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
-                     size_t *lds, int *lds_stride, LaunchShape *used);
+                     size_t *lds, int *lds_stride, LaunchShape *used, uint64_t min_histories = 0);
 void quenched_release(cls_problem *p);
 
 }  // namespace rt

@@ -215,6 +215,7 @@ bool launch_round(cls_server *s, RoundSlot &sl, cls_status *err)
     a.nprobs = n;
     a.lds_stride = stride;
     a.refill_min = used.refill_min;
+    a.slots = used.slots;
     hipError_t e = hipMemcpyAsync(sl.dev, sl.host, probs_bytes + items_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_track(v, a, grid, block, lds, st);
     if (e == hipSuccess) e = hipEventRecord(sl.ev, st);

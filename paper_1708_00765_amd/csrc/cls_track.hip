@@ -514,18 +514,22 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     const int lane = (int)(threadIdx.x & 63u);
     const int wid = (int)(threadIdx.x >> 6);
     const int KP = A.lds_stride;
-    // per wave: two tally buffers of KP doubles, then the score sum and score
-    // square sum of each slot, then kSlotCounters 32-bit counters per slot
-    double *const wbuf = lds + (size_t)wid * (2u * (size_t)KP + kWaveExtraDoubles);
-    double *const wsum = wbuf + 2 * KP;
+    const int nslots = A.slots;
+    // per wave: one or two tally buffers of KP doubles, then the score sum and
+    // score square sum of each slot, then kSlotCounters 32-bit counters per
+    // slot, then the material rows of each slot
+    double *const wbuf = lds + (size_t)wid * ((size_t)nslots * (size_t)KP + kWaveExtraDoubles);
+    double *const wsum = wbuf + nslots * KP;
     uint32_t *const wctr = (uint32_t *)(wsum + 4);    // [slot][kSlotCounters]
     MatRow<R> *const wmat = (MatRow<R> *)(wsum + 4 + kSlotCounters);   // [slot][material]
-    for (int i = lane; i < 2 * KP + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
+    for (int i = lane; i < nslots * KP + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
 
     // Wave-uniform state of the two chunk slots, kept as two named records
     // (never indexed by a run-time value, so that they stay in scalar
     // registers): C receives new histories and owns tally buffer cp, O is the
-    // other one (buffer cp ^ 1) whose stragglers may still be in flight.
+    // other one (buffer cp ^ 1) whose stragglers may still be in flight. With
+    // a single buffer (large meshes) O stays closed and a new chunk is taken
+    // only once C has been flushed.
     SlotState C = {0, 0, 0, 0, 0, 0}, O = {0, 0, 0, 0, 0, 0};
     int cp = 0;
     bool queue_empty = false;
@@ -547,7 +551,8 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
         // chunk cannot serve wait for the next step.
         uint64_t dead = ballot(!L.alive);
         if (dead != 0 && (dead == ~0ull || popc(dead) >= (uint32_t)A.refill_min)) {
-            if ((!C.open || C.next == C.cnt) && !O.open && !queue_empty) {
+            const bool slot_free = nslots == 2 ? ((!C.open || C.next == C.cnt) && !O.open) : !C.open;
+            if (slot_free && !queue_empty) {
                 uint64_t got = 0;
                 if (lane == 0) got = atomicAdd((unsigned long long *)A.queue_head, 1ull);
                 // lane 0's value, made wave-uniform so that the slot state
@@ -568,14 +573,16 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                     const uint64_t first = (P.chunk_base + item - starts[lo]) * P.chunk;
                     const uint64_t rest = P.histories - first;
                     // the new chunk goes to the free slot, which becomes current
-                    O = C;
+                    if (nslots == 2) {
+                        O = C;
+                        cp ^= 1;
+                    }
                     C.h0 = first;
                     C.cnt = (uint32_t)(rest < P.chunk ? rest : P.chunk);
                     C.next = 0;
                     C.live = 0;
                     C.pid = lo;
                     C.open = 1;
-                    cp ^= 1;
                     // the new slot's material rows; no lane of this wave reads
                     // them before its next event step, and a wave's LDS
                     // operations complete in order
