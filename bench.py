@@ -254,6 +254,34 @@ def run_paper_ref_rows(cls, torch, stream, histories, cls_histories):
     return out
 
 
+def run_quenched_leg(cls, torch, stream, perf_model, histories):
+    """The quenched d = 1 reference kernel on one paper case (Table 3, case 1a,
+    suite I slab, the paper's 1e4 realizations) at `histories` histories per
+    realization: rate and roofline of the kernel (FP64)."""
+    from paper_1708_00765_amd.inputs import paper_case
+    s = paper_case("1a", 1, "I", histories=1, seed=880001)
+    p = make_problem(cls, s, False)
+    cls.cls_set_stream(p, stream)
+    M = paper_realizations("I", "1a")
+    cls.cls_run_quenched(p, 10, 10, s.seed + 1)                    # warm the code object
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cls.cls_run_quenched(p, M, histories, s.seed)
+    g, _, _ = cls.cls_read_quenched(p, s.nbins)
+    wall = time.perf_counter() - t0
+    cls.cls_destroy_problem(p)
+    n = M * histories
+    slots = perf_model.quenched_slots(True, not s.collision, s.source == 0, n, g.flights, g.collisions, g.scatters)
+    achieved = slots / (g.track_ms * 1e-3) / 1e12
+    peak = perf_model.PEAK_SLOTS_PER_S / 1e12
+    return {"workload": f"quenched d=1 slab, Table 3 case 1a suite I: {M} realizations x {histories} histories, "
+                        f"{s.nbins} bins, track-length flux, FP64",
+            "value": n / wall, "unit": "histories/s", "wall_ms": 1e3 * wall, "kernel_ms": g.track_ms,
+            "flights_per_history": g.flights / n, "layers_per_realization": g.layers / M,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
+                         "frac": achieved / peak, "algorithmic_slots": slots}}
+
+
 def run_ext2d_comparison(cls, torch, stream, steps):
     """The 256 uneven ext2d sets (1e4..1e7 histories, 100..1000 bins): one batched
     FP32 persistent launch per pass vs one plain FP64 launch per set."""
@@ -353,6 +381,8 @@ def main() -> int:
                          "(0 = skip; the paper used 1e6), at the paper's realization counts")
     ap.add_argument("--paper-ref-cls", type=float, default=1e9,
                     help="histories of the CLS run compared with each reference row (0 = skip)")
+    ap.add_argument("--quenched-histories", type=float, default=1e5,
+                    help="histories per realization of the quenched d = 1 kernel leg (0 = skip)")
     ap.add_argument("--paper-out", default="", help="write the per-row results of --paper-rows to this JSON file")
     args = ap.parse_args()
 
@@ -445,6 +475,13 @@ def main() -> int:
         ext2d = run_ext2d_comparison(cls, torch, stream, args.ext2d_steps)
         log(f"ext2d 256 sets: fp32 batched {ext2d['fp32_batched_value']:.4g} hist/s, fp64 plain "
             f"{ext2d['fp64_plain_value']:.4g} hist/s, ratio {ext2d['ratio']:.2f}")
+
+    # ---- quenched d = 1 reference kernel -------------------------------------------
+    quenched = None
+    if args.quenched_histories > 0:
+        quenched = run_quenched_leg(cls, torch, stream, perf_model, int(args.quenched_histories))
+        log(f"quenched d=1: {quenched['value']:.4g} hist/s, kernel {quenched['kernel_ms']:.1f} ms, "
+            f"{quenched['flights_per_history']:.2f} flights/hist, roofline frac {quenched['roofline']['frac']:.3f}")
 
     # ---- served: Poisson request stream through the continuous-batching server --
     served = None
@@ -570,6 +607,7 @@ def main() -> int:
         "ext2d_batched_vs_fp64_plain": ext2d,
         "paper_rows": paper,
         "paper_reference_rows": paper_ref,
+        "quenched_d1": quenched,
     }
     print(json.dumps(line), flush=True)
     return 0

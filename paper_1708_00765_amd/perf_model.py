@@ -95,6 +95,29 @@ def algorithmic_slots(geom: str, histories: int, flights: int, scatters: int, la
             + lateral * 2 * F32)
 
 
+def quenched_slots(slab: bool, track: bool, face_source: bool, histories: int, flights: int, collisions: int,
+                   scatters: int) -> float:
+    """Algorithmic VALU slots of a quenched-disorder run in d = 1 (Section 3),
+    FP64 throughout: the realization's layers fix every interface, so a flight
+    samples only the collision distance and compares it with the distance to
+    the face of its layer. Building the layers (about rho L cells per
+    realization, against N x flights of transport) is left out."""
+    step = PHILOX + _price(False, i32=5, f64=2)                  # block, uniforms to FP64
+    flight = (_price(False, log=1, rcp=3)                          # -ln u / Sigma, (face - x) / mu, 1 / |mu|
+              + _price(False, i32=2 + 1 + 1 + 4 + 2,               # material, face select, compare, leak/layer tests
+                       f64=1 + 1))                                 # face - x, move
+    if track:
+        flight += _price(False, i32=2 * 3 + 2 + 4, f64=2 + 6 + 1)   # 2 bins, ordering, 4 LDS addresses; partials
+    coll = _price(False, f64=1) + (0.0 if track else _price(False, rcp=1, i32=3, f64=2))
+    scatter = _price(False, f64=2) if slab else _price(False, i32=2)
+    if face_source:
+        source = _price(False, sqrt=1) if slab else 0.0
+    else:
+        source = _price(False, f64=3, i32=6 * 3)                  # x, mu, layer by bisection
+    return ((histories + flights) * step + flights * flight + collisions * coll + scatters * scatter
+            + histories * source)
+
+
 def per_unit_table(fp32: bool = True) -> dict:
     """Slots per unit of work, for the design notes."""
     return {g: {"step": step_slots(fp32), "flight": flight_slots(g, fp32), "scatter": scatter_slots(g, fp32),
