@@ -199,6 +199,34 @@ def test_results_do_not_depend_on_launch_shape_and_autotune(cls):
             cls.cls_destroy_problem(p)
 
 
+def test_single_tally_buffer_mode_matches_oracle(cls):
+    """A 1000-bin mesh with chunks of at least 2048 histories runs with one LDS
+    tally buffer per wave (more waves resident than with two); with chunks of
+    at most 1024 histories the same problem runs with two buffers. Both give
+    the oracle's counts exactly (FP64 on the same streams) and its flux to
+    rounding (the chunking changes the order of the sums)."""
+    s = Spec(1, (0.5, 1.5), (0.5, 0.9), (1.0, 0.3), 1000, 48_000_000, 31)
+    _print("single-buffer case: rod, 1000 bins, 4.8e7 histories")
+    o = run_oracle(s)
+    results = []
+    try:
+        for max_chunk in (0, 1024):
+            cls.cls_set_launch_config(0, 0, max_chunk, 0)
+            g, flux, _, _ = run_gpu(s)
+            _print("max_chunk", max_chunk, "histories per chunk", g["histories"] / g["batches"])
+            results.append((g, flux))
+    finally:
+        cls.cls_set_launch_config(0, 0, 0, 0)
+    (g1, f1), (g2, f2) = results
+    assert g1["histories"] / g1["batches"] >= 2048 and g2["histories"] / g2["batches"] <= 1024
+    for g, f in results:
+        for k, ok in (("transmitted", o.transmitted), ("reflected", o.reflected), ("absorbed", o.absorbed),
+                      ("flights", o.flights), ("collisions", o.collisions), ("scatters", o.scatters),
+                      ("interface_crossings", o.interfaces)):
+            assert g[k] == ok, k
+        np.testing.assert_allclose(f, o.flux, rtol=1e-9, atol=1e-12)
+
+
 def test_caller_owned_memory_and_stream(cls):
     import torch
     s = workload("cube3d_track", histories=200_000)[2]
