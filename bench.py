@@ -294,13 +294,22 @@ def run_ext2d_comparison(cls, torch, stream, steps):
     try:
         for p in p32 + p64:
             cls.cls_set_stream(p, stream)
-        cls.cls_run_batch(p32, hist, [s.seed for s in specs])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(steps):
-            cls.cls_run_batch(p32, hist, [s.seed + k + 1 for s in specs])
-        torch.cuda.synchronize()
-        w32 = (time.perf_counter() - t0) / steps
+        def time_batched():
+            cls.cls_run_batch(p32, hist, [s.seed for s in specs])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(steps):
+                cls.cls_run_batch(p32, hist, [s.seed + k + 1 for s in specs])
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / steps
+
+        # default launch configuration, then the autotuner's choice for these sets
+        # (timed before and after the tuned runs: the order is not what differs)
+        w_default = time_batched()
+        cfg, tuned_rate = cls.cls_autotune(p32, hist, sample_histories=20_000_000)
+        w32 = time_batched()
+        cls.cls_set_launch_config(0, 0, 0, 0)         # the FP64 plain runs use the defaults
+        w_default = min(w_default, time_batched())
         for p, s in zip(p64[:8], specs[:8]):
             cls.cls_run(p, min(s.histories, 10000), s.seed)
         torch.cuda.synchronize()
@@ -315,7 +324,8 @@ def run_ext2d_comparison(cls, torch, stream, steps):
             cls.cls_destroy_problem(p)
     return {"sets": len(specs), "histories": total, "fp32_batched_value": total / w32,
             "fp64_plain_value": total / w64, "ratio": w64 / w32, "fp32_batched_ms": 1e3 * w32,
-            "fp64_plain_ms": 1e3 * w64, "unit": "histories/s"}
+            "fp64_plain_ms": 1e3 * w64, "unit": "histories/s", "autotuned_config": cfg,
+            "fp32_batched_default_config_value": total / w_default}
 
 
 def run_served(cls, seconds, rate):
@@ -473,7 +483,9 @@ def main() -> int:
     ext2d = None
     if args.ext2d_steps > 0:
         ext2d = run_ext2d_comparison(cls, torch, stream, args.ext2d_steps)
-        log(f"ext2d 256 sets: fp32 batched {ext2d['fp32_batched_value']:.4g} hist/s, fp64 plain "
+        log(f"ext2d 256 sets: fp32 batched {ext2d['fp32_batched_value']:.4g} hist/s (autotuned "
+            f"{ext2d['autotuned_config']}; default configuration "
+            f"{ext2d['fp32_batched_default_config_value']:.4g}), fp64 plain "
             f"{ext2d['fp64_plain_value']:.4g} hist/s, ratio {ext2d['ratio']:.2f}")
 
     # ---- quenched d = 1 reference kernel -------------------------------------------
