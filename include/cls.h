@@ -153,6 +153,12 @@ typedef struct {
 /* Copy the results of the last completed run. flux and flux_sigma (nbins doubles
  * each, may be NULL) receive the bin-averaged scalar flux per history and its
  * batch-means one-sigma error; nbins must equal the problem's mesh size.
+ * The event counts (flights, collisions, scatters, crossings, reflections) are
+ * summed per work chunk in 32 bits before they reach these 64-bit totals: a
+ * chunk must hold fewer than 2^32 events of each kind, i.e. max_chunk times the
+ * mean flights per history below 4.29e9 (with the default max_chunk of 16384,
+ * histories of up to ~2.6e5 flights on average). T, R, A and the flux do not
+ * depend on it.
  * Errors: CLS_ERR_STATE (no completed run), CLS_ERR_NOT_READY, CLS_ERR_INVALID_ARG,
  * CLS_ERR_EVENT_CAP (results are still written). */
 cls_status cls_read_tallies(const cls_problem *p, cls_tallies *out, double *flux,
@@ -212,7 +218,10 @@ cls_status cls_get_launch_config(cls_launch_config *cfg);
  * launch, make the fastest the process-wide launch configuration and return it
  * in *best (and its rate in histories/s in *best_rate, 0 when it came from the
  * cache). When the environment variable CLS_AUTOTUNE_CACHE names a file,
- * results are cached there per device, kernel variant and mesh-size class. */
+ * results are cached there per device, kernel variant and mesh-size class.
+ * The calibration runs use the problems themselves: afterwards their stored
+ * results are those of the last calibration run, so run them again before
+ * reading tallies. */
 cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories, int n,
                         uint64_t sample_histories, cls_launch_config *best, double *best_rate);
 

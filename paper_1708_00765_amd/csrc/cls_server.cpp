@@ -96,6 +96,8 @@ double seconds_since(const cls_server *s, Clock::time_point t)
     return std::chrono::duration<double>(t - s->t0).count();
 }
 
+// A request reaches its final state (under the lock); waiters are woken on
+// every path, failures included.
 void finish(cls_server *s, Request *r, cls_status err)
 {
     r->state = err == CLS_OK ? RQ_DONE : RQ_FAILED;
@@ -109,6 +111,7 @@ void finish(cls_server *s, Request *r, cls_status err)
         ++s->failed;
     }
     s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+    s->cv_done.notify_all();
 }
 
 // Admission (under the lock): reset the request's tallies on its stream.
@@ -284,7 +287,6 @@ void worker_main(cls_server *s)
             sl.parts.clear();
         }
         // results that have landed
-        bool any_done = false;
         for (size_t i = 0; i < s->active.size();) {
             Request *r = s->active[i];
             if (r->state == RQ_FINALIZING) {
@@ -302,13 +304,11 @@ void worker_main(cls_server *s)
                     } else {
                         finish(s, r, hip_fail(q, "result copy"));
                     }
-                    any_done = true;
                     continue;      // finish() removed active[i]
                 }
             }
             ++i;
         }
-        if (any_done) s->cv_done.notify_all();
         // launch rounds into free slots
         bool launched = false;
         for (RoundSlot &sl : s->slots) {
@@ -429,18 +429,23 @@ cls_status cls_server_wait(cls_server *s, uint64_t ticket, double timeout_s)
 {
     if (!s) return fail(CLS_ERR_INVALID_ARG, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->all.find(ticket);
-    if (it == s->all.end()) return fail(CLS_ERR_INVALID_ARG, "unknown ticket");
-    const Request *r = it->second;
     const auto deadline = Clock::now() + std::chrono::duration_cast<Clock::duration>(
                                              std::chrono::duration<double>(timeout_s > 0 ? timeout_s : 1e9));
-    while (r->state != RQ_DONE && r->state != RQ_FAILED) {
-        if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout &&
-            r->state != RQ_DONE && r->state != RQ_FAILED)
+    for (;;) {
+        // looked up again after every wake: another thread may have released it
+        auto it = s->all.find(ticket);
+        if (it == s->all.end()) return fail(CLS_ERR_INVALID_ARG, "unknown or released ticket");
+        const Request *r = it->second;
+        if (r->state == RQ_DONE) return CLS_OK;
+        if (r->state == RQ_FAILED) return fail(r->error, "request failed");
+        if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout) {
+            it = s->all.find(ticket);
+            if (it == s->all.end()) return fail(CLS_ERR_INVALID_ARG, "unknown or released ticket");
+            if (it->second->state == RQ_DONE) return CLS_OK;
+            if (it->second->state == RQ_FAILED) return fail(it->second->error, "request failed");
             return CLS_ERR_NOT_READY;
+        }
     }
-    if (r->state == RQ_FAILED) return fail(r->error, "request failed");
-    return CLS_OK;
 }
 
 cls_status cls_server_request_info(cls_server *s, uint64_t ticket, cls_request_info *info)
