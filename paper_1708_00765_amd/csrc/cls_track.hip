@@ -298,19 +298,26 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         // particle on that face), which never wins
         const double xh = L.ux > 0 ? P.Ld - L.x : L.x;
         R lb = (R)xh * MM::abs_(L.iux);
-        int ax = 0;
+        // which face is nearest: y beats x, then z beats both (masks, not an
+        // axis index: the event tests below use them directly)
+        bool ny = false, nz = false;
         if (AXES >= 2) {
             const R l = L.dy * L.aiuy;
-            if (l < lb) { lb = l; ax = 1; }
+            ny = l < lb;
+            lb = ny ? l : lb;
         }
         if (AXES >= 3) {
             const R l = L.dz * L.aiuz;
-            if (l < lb) { lb = l; ax = 2; }
+            nz = l < lb;
+            lb = nz ? l : lb;
         }
         const bool bnd = (lb <= lc) && (lb <= li);
         const bool coll = !bnd && (lc <= li);
         R s = bnd ? lb : (coll ? lc : li);
-        if (FP32) s = s > (R)0 ? s : (R)0;      // a face already passed by rounding: cross at once
+        // a face already passed by rounding: cross at once. s is never NaN (a
+        // NaN face distance never wins), so the FP32 clamp at 0 is an integer
+        // max of the bit pattern (negative floats are negative integers)
+        if (FP32) s = __int_as_float(max(__float_as_int(s), 0));
         const double xa = L.x;
         const int ka0 = L.kcur;
         const R fa = L.fx;
@@ -320,7 +327,7 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         // FP64 puts a leaking particle exactly on its face; in FP32 the
         // history ends there anyway and the snap would only move the last
         // track-length partial by a rounding error
-        if (!FP32 && bnd && ax == 0) L.x = L.ux > 0 ? P.Ld : 0.0;
+        if (!FP32 && bnd && !ny && !nz) L.x = L.ux > 0 ? P.Ld : 0.0;
         // A lateral coordinate rounded past its face is harmless: the next
         // distance to that face is <= 0, so the particle reaches it at once.
         L.kcur = bin_of<R>(L.x, P.inv_dx, P.K, &L.fx);
@@ -365,9 +372,9 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         }
         // ---- the event (Section 4), written as selects: every lane evaluates
         //      the same instructions whichever event it meets ----
-        const bool leak = bnd && ax == 0;
-        const bool refl_y = AXES >= 2 && bnd && ax == 1;
-        const bool refl_z = AXES >= 3 && bnd && ax == 2;
+        const bool leak = bnd && !ny && !nz;
+        const bool refl_y = AXES >= 2 && bnd && ny && !nz;
+        const bool refl_z = AXES >= 3 && bnd && nz;
         const bool intf = !bnd && !coll;
         const bool scat = coll && unit<R>(B.k[2]) < mat.c;
         if (EST == EST_COLLISION) {
@@ -594,20 +601,23 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                 const uint32_t nd = popc(dead);
                 const uint32_t take = avail < nd ? avail : nd;
                 const uint32_t r = rank_in(dead);
-                // the r-th idle lane takes history C.h0 + C.next + r (written as
-                // selects: no branch, no copies of the lane state around one)
+                // the r-th idle lane takes history C.h0 + C.next + r (an
+                // exec-masked block: scalar values move straight into the
+                // lanes' registers, where selects would first copy them)
                 const bool nw = !L.alive && r < take;
-                L.slot = nw ? cp : L.slot;
-                L.tb = nw ? cp * KP : L.tb;
-                L.pid = nw ? C.pid : L.pid;
-                L.h = nw ? C.h0 + C.next + r : L.h;
-                L.step = nw ? 0u : L.step;
-                L.n_int = nw ? 0u : L.n_int;
-                L.n_scat = nw ? 0u : L.n_scat;
-                L.n_lat = nw ? 0u : L.n_lat;
-                L.tscore = nw ? 0.0 : L.tscore;
-                if (TRACE) L.hash = nw ? 0xCBF29CE484222325ull : L.hash;
-                L.alive = L.alive || nw;
+                if (nw) {
+                    L.slot = cp;
+                    L.tb = cp * KP;
+                    L.pid = C.pid;
+                    L.h = C.h0 + C.next + r;
+                    L.step = 0u;
+                    L.n_int = 0u;
+                    L.n_scat = 0u;
+                    L.n_lat = 0u;
+                    L.tscore = 0.0;
+                    if (TRACE) L.hash = 0xCBF29CE484222325ull;
+                    L.alive = true;
+                }
                 C.next += take;
                 C.live += take;
                 dead = ballot(!L.alive);
