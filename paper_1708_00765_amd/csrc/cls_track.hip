@@ -206,14 +206,15 @@ struct Lane {
     bool alive;
 };
 
-// Flux bin of x (truncation equals floor for x >= 0; positions rounded just
-// outside [0, L] map to the end bins) and, in FP32, the position of x inside
-// that bin in bin widths.
+// Flux bin of x and, in FP32, the position of x inside that bin in bin
+// widths. Positions lie in [0, L] up to the rounding of a leaking FP32 move
+// (never below -dx), and truncation maps t in (-1, 0) to bin 0, so only the
+// upper end needs a clamp (x = L, or just beyond, is in bin K - 1).
 template <typename R>
 __device__ __forceinline__ int bin_of(double x, double inv_dx, int K, R *frac)
 {
     const double t = x * inv_dx;
-    const int k = min(max((int)t, 0), K - 1);
+    const int k = min((int)t, K - 1);
     if (sizeof(R) == 4) *frac = (R)(t - (double)k);
     return k;
 }
@@ -341,7 +342,9 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         if (EST == EST_TRACK) {
             const double sd = (double)s;
             L.tscore += sd;
-            const bool up = L.x >= xa;
+            // s >= 0, so x moves with the sign of u_x (a move that rounds to
+            // zero stays in its bin, where the orientation does not matter)
+            const bool up = L.ux > 0;
             const int ka = up ? ka0 : L.kcur;
             const int kb = up ? L.kcur : ka0;
             const bool one = (ka == kb);
