@@ -174,7 +174,13 @@ cls_status cls_read_trace(const cls_problem *p, uint64_t *hash, uint32_t *flight
  * the slab flag, source, estimator and precision (CLS_ERR_INVALID_ARG
  * otherwise); histories[i] and seeds[i] belong to problems[i]. Every problem
  * receives the same tallies it would get from cls_run with the same histories
- * and seed. The launch uses the stream of problems[0] and is synchronous. */
+ * and seed (counts exactly, FP64 sums up to the order of additions) except
+ * flux_sigma: the per-bin error is a batch-means estimate over the work
+ * chunks, and in a batch a problem's chunks may be larger (sized for the whole
+ * batch, at least 256 of them per problem when its history count allows), so
+ * flux_sigma is an equally valid estimate from other batches. The same holds
+ * for a different launch configuration. The launch uses the stream of
+ * problems[0] and is synchronous. */
 cls_status cls_run_batch(cls_problem *const *problems, const uint64_t *histories,
                          const uint64_t *seeds, int n);
 

@@ -63,6 +63,8 @@ constexpr size_t kLdsLimit = 65536;
 constexpr int kDefaultRefillMin = 4;
 // smallest chunk (histories) for which one LDS tally buffer per wave pays
 constexpr uint64_t kSingleSlotMinChunk = 2048;
+// chunks (batches of the flux error) a problem of a batch keeps at least
+constexpr uint64_t kMinErrorBatches = 256;
 }  // namespace
 
 namespace cls {
@@ -184,6 +186,20 @@ uint64_t chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk)
     if (n / c < waves_total) c = std::max<uint64_t>(64, (n + waves_total - 1) / waves_total);
     c = std::min<uint64_t>(c, max_chunk);
     return std::max<uint64_t>(c, 1);
+}
+
+// In a batch the other problems keep the waves busy, so a small problem need
+// not be cut into a chunk per wave (which, with fine meshes, makes the chunk
+// flushes the dominant cost): chunks grow towards the size that gives the whole
+// batch about 32 chunks per wave (the density a single large problem gets),
+// while every problem keeps at least 256 chunks, the batches of its flux
+// error, when its history count allows.
+uint64_t batch_chunk_size(uint64_t n, uint64_t total, uint64_t waves_total, uint64_t max_chunk)
+{
+    const uint64_t c = chunk_size(n, waves_total, max_chunk);
+    const uint64_t c_all = (total + 32 * waves_total - 1) / (32 * waves_total);
+    const uint64_t c_err = (n + kMinErrorBatches - 1) / kMinErrorBatches;
+    return std::max(c, std::min(std::min(c_all, c_err), max_chunk));
 }
 
 void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,
@@ -672,10 +688,11 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     std::lock_guard<std::mutex> lk(g_batch_mu);
     int max_bins = 1;
     size_t rec_words = 0;
-    uint64_t min_hist = histories[0];
+    uint64_t min_hist = histories[0], total_hist = 0;
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
         min_hist = std::min(min_hist, histories[i]);
+        total_hist += histories[i];
         const uint64_t tn = trace_count(p, histories[i]);
         cls_status st = ensure_device(p, tn);
         if (st != CLS_OK) return st;
@@ -710,7 +727,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
         const uint64_t tn = trace_count(p, histories[i]);
-        const uint64_t chunk = chunk_size(histories[i], waves_total, (uint64_t)used.max_chunk);
+        const uint64_t chunk = batch_chunk_size(histories[i], total_hist, waves_total, (uint64_t)used.max_chunk);
         fill_dev_problem(p, histories[i], seeds[i], chunk, tn, &h_probs[i]);
         h_probs[i].record = d_rec + off;
         off += record_words(p->nbins);

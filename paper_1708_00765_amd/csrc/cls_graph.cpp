@@ -150,9 +150,11 @@ cls_status cls_batch_run(cls_batch *b, const uint64_t *histories, const uint64_t
     uint64_t *d_rec = (uint64_t *)(b->dev + b->probs_bytes + b->items_bytes);
     h_items[0] = 0;
     size_t off = 0;
+    uint64_t total = 0;
+    for (int i = 0; i < n; ++i) total += histories[i];
     for (int i = 0; i < n; ++i) {
         cls_problem *p = b->probs[i];
-        const uint64_t chunk = chunk_size(histories[i], b->waves_total, b->max_chunk);
+        const uint64_t chunk = batch_chunk_size(histories[i], total, b->waves_total, b->max_chunk);
         fill_dev_problem(p, histories[i], seeds[i], chunk, 0, &h_probs[i]);
         h_probs[i].record = d_rec + off;
         off += record_words(p->nbins);
