@@ -77,6 +77,10 @@ size_t workspace_bytes(int nbins, uint64_t trace_n);
 cls_status ensure_device(cls_problem *p, uint64_t trace_n);
 uint64_t trace_count(const cls_problem *p, uint64_t histories);
 uint64_t chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk);
+// Chunk of one problem run together with others (which fill the GPU): at most
+// `cap` histories, and at least 256 chunks when n allows (never below
+// chunk_size).
+uint64_t grouped_chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk, uint64_t cap);
 // Chunk of one problem of a batch whose problems hold `total` histories.
 uint64_t batch_chunk_size(uint64_t n, uint64_t total, uint64_t waves_total, uint64_t max_chunk);
 void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,

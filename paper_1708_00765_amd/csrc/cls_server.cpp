@@ -120,14 +120,17 @@ cls_status admit(cls_server *s, Request *r)
     cls_problem *p = r->p;
     cls_status st = ensure_device(p, 0);
     if (st != CLS_OK) return st;
-    // the same chunking a standalone run of this request would use
+    // chunks fixed by the request alone (never by the mix it meets): rounds
+    // are shared, so a small request need not be cut into a chunk per wave;
+    // a chunk stays within a round's share of one wave
     int grid, block, stride;
     size_t lds;
     LaunchShape sh;
     st = shape_for(variant_of(p), p->nbins, s->di, &grid, &block, &lds, &stride, &sh);
     if (st != CLS_OK) return st;
     const uint64_t waves_total = (uint64_t)grid * (uint64_t)(block / 64);
-    r->chunk = chunk_size(r->histories, waves_total, (uint64_t)sh.max_chunk);
+    const uint64_t round_share = std::max<uint64_t>(1, s->cfg.round_histories / waves_total);
+    r->chunk = grouped_chunk_size(r->histories, waves_total, (uint64_t)sh.max_chunk, round_share);
     r->n_chunks = (r->histories + r->chunk - 1) / r->chunk;
     if (p->has_run) HIP_TRY(hipEventSynchronize(p->ev_done));
     fill_dev_problem(p, r->histories, r->seed, r->chunk, 0, p->h_prob);
