@@ -399,7 +399,7 @@ def main() -> int:
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(CLS histories are independent: a multi-GPU run would shard history ranges "
-              "and all-reduce the tallies, which this build does not implement).", flush=True)
+              "and all-reduce the tallies, which this library does not implement).", flush=True)
         return 2
 
     import torch
