@@ -199,6 +199,29 @@ def test_results_do_not_depend_on_launch_shape_and_autotune(cls):
             cls.cls_destroy_problem(p)
 
 
+def test_batch_chunks_keep_error_batches(cls):
+    """In a batch a problem's chunks only grow (never more chunks than alone),
+    and it keeps at least min(256, n / 64) of them, the batches of its per-bin
+    flux error; counts stay those of the lone run."""
+    specs = workload("ext2d_batched", histories=None)[:24]
+    alone = [run_gpu(s, fp32=True)[0] for s in specs]
+    probs = [gpu_problem(s, fp32=True) for s in specs]
+    try:
+        cls.cls_run_batch(probs, [s.histories for s in specs], [s.seed for s in specs])
+        for s, p, g1 in zip(specs, probs, alone):
+            t, _, fsig = cls.cls_read_tallies(p, s.nbins)
+            g2 = tallies_dict(t)
+            _print(s.name, "histories", s.histories, "chunks alone", g1["batches"], "in the batch", g2["batches"])
+            assert g2["batches"] <= g1["batches"], s.name
+            assert g2["batches"] >= min(256, s.histories // 64), s.name
+            for k in COUNTS:
+                assert g1[k] == g2[k], (s.name, k)
+            assert np.all(np.isfinite(fsig))
+    finally:
+        for p in probs:
+            cls.cls_destroy_problem(p)
+
+
 def test_single_tally_buffer_mode_matches_oracle(cls):
     """A 1000-bin mesh with chunks of at least 2048 histories runs with one LDS
     tally buffer per wave (more waves resident than with two); with chunks of
