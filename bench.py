@@ -367,6 +367,46 @@ def run_served(cls, seconds, rate):
                         "histories log-uniform in [1e4, 1e8], 10-1000 bins, FP32 tracking"}
 
 
+def run_served_saturated(cls, rate, seconds):
+    """The served request mix at saturation: every request of `seconds` of a
+    Poisson stream at `rate` submitted at once; throughput over the makespan
+    (first submission to last result on the host) and the algorithmic VALU
+    roofline fraction of the served form."""
+    from paper_1708_00765_amd import perf_model
+    from paper_1708_00765_amd.inputs import served_requests
+    specs = [s for _, s in served_requests(rate_hz=rate, duration_s=seconds)]
+    probs = [make_problem(cls, s, fp32=True) for s in specs]
+    srv = cls.cls_server_create()
+    try:
+        tickets = [cls.cls_server_submit(srv, p, s.histories, s.seed) for p, s in zip(probs, specs)]
+        for tk in tickets:
+            cls.cls_server_wait(srv, tk, 600.0)
+        infos = [cls.cls_server_request_info(srv, tk) for tk in tickets]
+        stats = cls.cls_server_get_stats(srv)
+    finally:
+        cls.cls_server_destroy(srv)
+    try:
+        slots = 0.0
+        for p, s in zip(probs, specs):
+            t, _, _ = cls.cls_read_tallies(p, s.nbins)
+            slots += perf_model.algorithmic_slots(s.geom_name, t.histories, t.flights, t.scatters,
+                                                  t.lateral_reflections, fp32=True, track=not s.collision)
+    finally:
+        for p in probs:
+            cls.cls_destroy_problem(p)
+    span = max(i["done_s"] for i in infos) - min(i["submit_s"] for i in infos)
+    hist = sum(s.histories for s in specs)
+    achieved = slots / span / 1e12
+    peak = perf_model.PEAK_SLOTS_PER_S / 1e12
+    return {"requests": len(specs), "completed": stats["completed"], "failed": stats["failed"],
+            "histories": hist, "seconds": span, "value": hist / span, "unit": "histories/s",
+            "rounds": stats["rounds"],
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
+                         "frac": achieved / peak, "algorithmic_slots": slots},
+            "workload": f"served mix (as the Poisson stream), the {len(specs)} requests of {seconds:g} s at "
+                        f"{rate:g} requests/s submitted at once"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -381,6 +421,9 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="length of the served Poisson request stream (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
+    ap.add_argument("--saturate-seconds", type=float, default=2.0,
+                    help="served mix at saturation: requests of this many seconds at 600/s, "
+                         "submitted at once (0 = skip)")
     ap.add_argument("--ext2d-steps", type=int, default=2,
                     help="timed passes of the 256-set ext2d comparison (0 = skip)")
     ap.add_argument("--paper-rows", type=float, default=0,
@@ -501,6 +544,11 @@ def main() -> int:
         served = run_served(cls, args.serve_seconds, args.serve_rate)
         log(f"served: {served['completed']} requests, p50 {served['p50_ms']:.1f} ms, "
             f"p99 {served['p99_ms']:.1f} ms, {served['histories_per_s']:.4g} hist/s")
+    served_sat = None
+    if args.saturate_seconds > 0:
+        served_sat = run_served_saturated(cls, 600.0, args.saturate_seconds)
+        log(f"served at saturation: {served_sat['requests']} requests, {served_sat['value']:.4g} hist/s, "
+            f"roofline frac {served_sat['roofline']['frac']:.3f}")
 
     # ---- the paper's own benchmark rows ---------------------------------------
     paper = None
@@ -616,6 +664,7 @@ def main() -> int:
                      "kernel_ms": kernel_ms, "algorithmic_slots_per_launch": slots},
         "cpu_baseline": cpu,
         "served": served,
+        "served_saturated": served_sat,
         "ext2d_batched_vs_fp64_plain": ext2d,
         "paper_rows": paper,
         "paper_reference_rows": paper_ref,

@@ -187,7 +187,8 @@ cls_status cls_run_batch(cls_problem *const *problems, const uint64_t *histories
 /* Graph-captured batch: the same set of problems run repeatedly. The first
  * cls_batch_run captures reset, tracking, finalize and result copy of one
  * batched launch in a hipGraph on the batch's own stream; later runs replay it
- * with new history counts and seeds (launch shape fixed at creation).
+ * with new history counts and seeds (the launch shape is the one chosen for
+ * the first run's history counts).
  * Problems must satisfy the cls_run_batch rules, must not use CLS_F_TRACE, and
  * stay owned by the caller (they must outlive the batch). cls_batch_run is
  * synchronous; results are read with cls_read_tallies on each problem.
@@ -236,12 +237,19 @@ cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories,
  *                        admitted requests (0: 80% of the free device memory);
  *                        a request that does not fit waits in arrival order
  *                        (one is always admitted when nothing else is);
- *   round_histories      histories per batched launch ("round"; 0: 3e7);
+ *   round_histories      smallest size in histories of a batched launch
+ *                        ("round") when that much work is queued (0: 3e7); it
+ *                        also bounds a request's chunk size (about
+ *                        round_histories / resident waves, see below);
  *   max_inflight_rounds  launches queued on the GPU at once (0: 2; at most 8).
  * A worker thread admits requests, runs rounds of one persistent launch over
  * the next chunks of every admitted request of one kernel variant, and copies
- * each request's results back when its last chunk is done. Requests that
- * arrive while others run join the next round. Each result is the one
+ * each request's results back when its last chunk is done. A round holds at
+ * least round_histories and at least three of its largest chunks per resident
+ * wave (a round lasts at least as long as one wave takes for its largest
+ * chunk), shared equally between its requests: one with less left finishes in
+ * that round, the others get equal shares of the rest (at least one chunk).
+ * Requests that arrive while others run join the next round. Each result is the one
  * cls_run would give for the same problem, histories and seed (integer
  * tallies bitwise, FP64 sums up to atomic ordering). */
 typedef struct cls_server cls_server;

@@ -61,8 +61,6 @@ constexpr int kDefaultMaxChunk = 16384;
 constexpr uint64_t kDefaultMaxSteps = 100000000ull;
 constexpr size_t kLdsLimit = 65536;
 constexpr int kDefaultRefillMin = 4;
-// smallest chunk (histories) for which one LDS tally buffer per wave pays
-constexpr uint64_t kSingleSlotMinChunk = 2048;
 // chunks (batches of the flux error) a problem of a batch keeps at least
 constexpr uint64_t kMinErrorBatches = 256;
 }  // namespace
@@ -268,7 +266,8 @@ Variant variant_of(const cls_problem *p)
 // Launch shape. Each wave needs one or two LDS tally buffers (two let a
 // wave start its next chunk while the last histories of the previous one
 // finish; one halves the LDS, at the cost of waiting for those histories,
-// which only pays with chunks of several thousand histories);
+// which only pays when nearly all of the launch's histories sit in chunks of
+// several thousand histories);
 // a workgroup uses at most kLdsLimit. Unless the caller fixed them, the
 // workgroup size (1, 2, 4 or 8 waves) and the buffer count are the ones
 // that keep the most waves resident per compute unit (occupancy query; ties
@@ -276,7 +275,7 @@ Variant variant_of(const cls_problem *p)
 // measured fastest at equal residency) and the persistent grid holds as
 // many workgroups as the compute units keep resident at once.
 cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
-                     size_t *lds, int *lds_stride, LaunchShape *used, uint64_t min_histories)
+                     size_t *lds, int *lds_stride, LaunchShape *used, const SmallShareFn &small_share)
 {
     LaunchShape s = current_shape();
     int kp = max_bins + 1;
@@ -298,8 +297,7 @@ cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *
             }
             if (slots == 1) {
                 const uint64_t waves_total = (uint64_t)di.cus * (uint64_t)std::max(bpc, 1) * (uint64_t)c;
-                if (min_histories == 0 ||
-                    chunk_size(min_histories, waves_total, (uint64_t)s.max_chunk) < kSingleSlotMinChunk)
+                if (!small_share || small_share(waves_total, (uint64_t)s.max_chunk) > kSingleSlotMaxSmallShare)
                     continue;
             }
             if (bpc * c > best_bpc * best_waves) { best_waves = c; best_bpc = bpc; best_slots = slots; }
@@ -508,7 +506,10 @@ cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed)
     int grid, block, stride;
     size_t lds;
     LaunchShape used;
-    st = shape_for(variant_of(p), p->nbins, di, &grid, &block, &lds, &stride, &used, histories);
+    st = shape_for(variant_of(p), p->nbins, di, &grid, &block, &lds, &stride, &used,
+                   [histories](uint64_t waves_total, uint64_t max_chunk) {
+                       return chunk_size(histories, waves_total, max_chunk) < kSingleSlotMinChunk ? 1.0 : 0.0;
+                   });
     if (st != CLS_OK) return st;
     const uint64_t waves_total = (uint64_t)grid * (uint64_t)(block / 64);
     const uint64_t chunk = chunk_size(histories, waves_total, (uint64_t)used.max_chunk);
@@ -692,10 +693,9 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     std::lock_guard<std::mutex> lk(g_batch_mu);
     int max_bins = 1;
     size_t rec_words = 0;
-    uint64_t min_hist = histories[0], total_hist = 0;
+    uint64_t total_hist = 0;
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
-        min_hist = std::min(min_hist, histories[i]);
         total_hist += histories[i];
         const uint64_t tn = trace_count(p, histories[i]);
         cls_status st = ensure_device(p, tn);
@@ -711,7 +711,15 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     int grid, block, stride;
     size_t lds;
     LaunchShape used;
-    st = shape_for(variant_of(problems[0]), max_bins, di, &grid, &block, &lds, &stride, &used, min_hist);
+    st = shape_for(variant_of(problems[0]), max_bins, di, &grid, &block, &lds, &stride, &used,
+                   [&](uint64_t waves_total, uint64_t max_chunk) {
+                       double small = 0.0;
+                       for (int i = 0; i < n; ++i)
+                           if (batch_chunk_size(histories[i], total_hist, waves_total, max_chunk) <
+                               kSingleSlotMinChunk)
+                               small += (double)histories[i];
+                       return small / (double)total_hist;
+                   });
     if (st != CLS_OK) return st;
     const size_t probs_bytes = align256((size_t)n * sizeof(DevProblem));
     const size_t items_bytes = align256(((size_t)n + 2) * sizeof(uint64_t));

@@ -3,7 +3,8 @@
 // for every later run of the same set of problems. The graph reads the
 // problem records and work-queue prefix sums from pinned host memory that each
 // run rewrites, so histories and seeds may change between replays; the launch
-// shape (grid, workgroup, LDS) is fixed at capture.
+// shape (grid, workgroup, LDS buffers per wave) is chosen for the history
+// counts of the first run and fixed at its capture.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +25,7 @@ struct cls_batch {
     char *dev = nullptr;
     char *host = nullptr;
     size_t probs_bytes = 0, items_bytes = 0, rec_words = 0;
+    int max_bins = 1;
     int grid = 0, block = 0, stride = 0, refill_min = 1, slots = 2;
     size_t lds = 0;
     uint64_t max_chunk = 0, waves_total = 0;
@@ -104,20 +106,12 @@ cls_status cls_batch_create(cls_problem *const *problems, int n, cls_batch **out
     b->probs.assign(problems, problems + n);
     b->v = variant_of(problems[0]);
     b->device = di.id;
-    int max_bins = 1;
     for (int i = 0; i < n; ++i) {
         st = ensure_device(problems[i], 0);
         if (st != CLS_OK) { batch_release(b); delete b; return st; }
-        max_bins = std::max(max_bins, problems[i]->nbins);
+        b->max_bins = std::max(b->max_bins, problems[i]->nbins);
         b->rec_words += record_words(problems[i]->nbins);
     }
-    LaunchShape used;
-    st = shape_for(b->v, max_bins, di, &b->grid, &b->block, &b->lds, &b->stride, &used);
-    if (st != CLS_OK) { batch_release(b); delete b; return st; }
-    b->refill_min = used.refill_min;
-    b->slots = used.slots;
-    b->max_chunk = (uint64_t)used.max_chunk;
-    b->waves_total = (uint64_t)b->grid * (uint64_t)(b->block / 64);
     b->probs_bytes = align256((size_t)n * sizeof(DevProblem));
     b->items_bytes = align256(((size_t)n + 2) * sizeof(uint64_t));
     const size_t bytes = b->probs_bytes + b->items_bytes + align256(b->rec_words * sizeof(uint64_t));
@@ -152,6 +146,27 @@ cls_status cls_batch_run(cls_batch *b, const uint64_t *histories, const uint64_t
     size_t off = 0;
     uint64_t total = 0;
     for (int i = 0; i < n; ++i) total += histories[i];
+    if (!b->exec) {
+        // launch shape for the history counts of this (first) run
+        DeviceInfo di;
+        cls_status st = device_info(&di);
+        if (st != CLS_OK) return st;
+        LaunchShape used;
+        st = shape_for(b->v, b->max_bins, di, &b->grid, &b->block, &b->lds, &b->stride, &used,
+                       [&](uint64_t waves_total, uint64_t max_chunk) {
+                           double small = 0.0;
+                           for (int i = 0; i < n; ++i)
+                               if (batch_chunk_size(histories[i], total, waves_total, max_chunk) <
+                                   kSingleSlotMinChunk)
+                                   small += (double)histories[i];
+                           return small / (double)total;
+                       });
+        if (st != CLS_OK) return st;
+        b->refill_min = used.refill_min;
+        b->slots = used.slots;
+        b->max_chunk = (uint64_t)used.max_chunk;
+        b->waves_total = (uint64_t)b->grid * (uint64_t)(b->block / 64);
+    }
     for (int i = 0; i < n; ++i) {
         cls_problem *p = b->probs[i];
         const uint64_t chunk = batch_chunk_size(histories[i], total, b->waves_total, b->max_chunk);

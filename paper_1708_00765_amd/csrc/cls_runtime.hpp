@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+#include <functional>
 #include <string>
 
 #include "cls.h"
@@ -87,12 +88,20 @@ void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, u
                       uint64_t trace_n, DevProblem *out);
 Variant variant_of(const cls_problem *p);
 bool same_variant(const Variant &a, const Variant &b);
-// min_histories: the smallest history count among the launch's problems, or
-// 0 when it is not known (graph batches, the server): one tally buffer per
-// wave is considered only when that problem's chunks would hold at least
-// kSingleSlotMinChunk histories.
+// One LDS tally buffer per wave (instead of two) doubles the waves an LDS-bound
+// launch keeps resident, but a wave then waits for the last histories of its
+// chunk before it claims the next; that wait pays only for chunks of at least
+// kSingleSlotMinChunk histories. small_share(waves_total, max_chunk) returns
+// the share of the launch's histories that sit in smaller chunks on a grid of
+// waves_total waves; one buffer per wave is considered only when it is at most
+// kSingleSlotMaxSmallShare. Empty when the chunks are not known at launch-shape
+// time (graph batches): then every wave gets two buffers.
+constexpr uint64_t kSingleSlotMinChunk = 2048;
+constexpr double kSingleSlotMaxSmallShare = 0.2;
+using SmallShareFn = std::function<double(uint64_t waves_total, uint64_t max_chunk)>;
 cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
-                     size_t *lds, int *lds_stride, LaunchShape *used, uint64_t min_histories = 0);
+                     size_t *lds, int *lds_stride, LaunchShape *used,
+                     const SmallShareFn &small_share = SmallShareFn());
 void quenched_release(cls_problem *p);
 
 }  // namespace rt

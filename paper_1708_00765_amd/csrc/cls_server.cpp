@@ -5,7 +5,9 @@
 // the HBM budget; an admitted request's tallies stay resident until it
 // completes. A worker thread issues "rounds": one batched persistent launch of
 // the tracking kernel over the next chunks of every admitted request of one
-// kernel variant (round-robin over variants), sized to about round_histories.
+// kernel variant (round-robin over variants), of at least round_histories and
+// at least kRoundChunksPerWave of the largest chunks per wave, shared equally
+// between the requests, largest chunks first in the work queue.
 // Requests admitted while others are on the GPU join the next round, so their
 // work overlaps on the device; up to max_inflight_rounds launches are queued
 // at once on two streams. A request whose last chunk has completed gets its
@@ -36,6 +38,9 @@ using namespace cls::rt;
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// Chunks of the largest size per wave that a round holds at least.
+constexpr double kRoundChunksPerWave = 3.0;
 
 enum ReqState { RQ_PENDING, RQ_ACTIVE, RQ_FINALIZING, RQ_DONE, RQ_FAILED };
 
@@ -180,23 +185,75 @@ bool launch_round(cls_server *s, RoundSlot &sl, cls_status *err)
     for (Request *r : s->active)
         if (r->state == RQ_ACTIVE && r->next_chunk < r->n_chunks && same_variant(variant_of(r->p), v))
             reqs.push_back(r);
-    const uint64_t quota = std::max<uint64_t>(1, s->cfg.round_histories / reqs.size());
-    sl.parts.clear();
+    // Launch shape first: its wave count sizes the round. Chunks were fixed at
+    // admission, so the share of histories in small chunks does not depend on
+    // the grid.
+    auto small_share_of = [](const std::vector<RoundPart> &parts) {
+        double small = 0.0, all = 0.0;
+        for (const RoundPart &part : parts) {
+            const double h = (double)part.chunks * (double)part.r->chunk;
+            all += h;
+            if (part.r->chunk < kSingleSlotMinChunk) small += h;
+        }
+        return all > 0.0 ? small / all : 1.0;
+    };
     int max_bins = 1;
+    uint64_t max_chunk = 1;
+    sl.parts.clear();
     for (Request *r : reqs) {
-        const uint64_t want = std::max<uint64_t>(1, (quota + r->chunk - 1) / r->chunk);
-        const uint64_t take = std::min(want, r->n_chunks - r->next_chunk);
-        sl.parts.push_back({r, take});
+        sl.parts.push_back({r, r->n_chunks - r->next_chunk});
         max_bins = std::max(max_bins, r->p->nbins);
+        max_chunk = std::max(max_chunk, r->chunk);
     }
-    const int n = (int)sl.parts.size();
-    const size_t probs_bytes = align256((size_t)n * sizeof(DevProblem));
-    const size_t items_bytes = align256(((size_t)n + 2) * sizeof(uint64_t));
     int grid = 0, block = 0, stride = 0;
     size_t lds = 0;
     LaunchShape used;
-    *err = ensure_slot(s, sl, probs_bytes + items_bytes);
-    if (*err == CLS_OK) *err = shape_for(v, max_bins, s->di, &grid, &block, &lds, &stride, &used);
+    const double backlog_share = small_share_of(sl.parts);
+    *err = shape_for(v, max_bins, s->di, &grid, &block, &lds, &stride, &used,
+                     [backlog_share](uint64_t, uint64_t) { return backlog_share; });
+    // Round size: at least round_histories, and enough for kRoundChunksPerWave
+    // of the largest chunks per wave (a round lasts at least as long as its
+    // largest chunk takes one wave, so smaller rounds leave most waves idle).
+    const uint64_t waves = *err == CLS_OK ? (uint64_t)grid * (uint64_t)(block / 64) : 1;
+    const double budget = std::max((double)s->cfg.round_histories,
+                                   (double)kRoundChunksPerWave * (double)waves * (double)max_chunk);
+    // Water-filling: requests with less left than an equal share finish in
+    // this round; the others get the equal share of what remains (at least
+    // one chunk each).
+    std::vector<Request *> by_left = reqs;
+    auto left = [](const Request *r) { return (double)(r->n_chunks - r->next_chunk) * (double)r->chunk; };
+    std::sort(by_left.begin(), by_left.end(), [&](const Request *a, const Request *b) { return left(a) < left(b); });
+    double rest = budget, level = 0.0;
+    size_t i_full = 0;
+    for (; i_full < by_left.size(); ++i_full) {
+        const double share = rest / (double)(by_left.size() - i_full);
+        if (left(by_left[i_full]) > share) {
+            level = share;
+            break;
+        }
+        rest -= left(by_left[i_full]);
+    }
+    sl.parts.clear();
+    for (size_t i = 0; i < by_left.size(); ++i) {
+        Request *r = by_left[i];
+        const uint64_t rem = r->n_chunks - r->next_chunk;
+        const uint64_t take = i < i_full ? rem
+                                         : std::min(rem, std::max<uint64_t>(1, (uint64_t)(level / (double)r->chunk)));
+        sl.parts.push_back({r, take});
+    }
+    // largest chunks first: the work queue hands items out in order, so the
+    // small chunks fill the waves that finish early
+    std::stable_sort(sl.parts.begin(), sl.parts.end(),
+                     [](const RoundPart &a, const RoundPart &b) { return a.r->chunk > b.r->chunk; });
+    const int n = (int)sl.parts.size();
+    const size_t probs_bytes = align256((size_t)n * sizeof(DevProblem));
+    const size_t items_bytes = align256(((size_t)n + 2) * sizeof(uint64_t));
+    if (*err == CLS_OK) {
+        const double share = small_share_of(sl.parts);
+        *err = shape_for(v, max_bins, s->di, &grid, &block, &lds, &stride, &used,
+                         [share](uint64_t, uint64_t) { return share; });
+    }
+    if (*err == CLS_OK) *err = ensure_slot(s, sl, probs_bytes + items_bytes);
     if (*err != CLS_OK) {
         // these requests cannot be launched: fail them rather than retry forever
         for (RoundPart &part : sl.parts) finish(s, part.r, *err);

@@ -222,6 +222,79 @@ def test_batch_chunks_keep_error_batches(cls):
             cls.cls_destroy_problem(p)
 
 
+def _fine_mesh_mix(big_histories, n_big, n_small, seed):
+    """n_big cube3d problems with 700-1000 bins and big_histories each, plus
+    n_small problems of 1e3 to 1e5 histories and 10 to 1000 bins (FP32)."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(n_big + n_small):
+        sig = tuple(float(v) for v in rng.uniform(0.2, 2.0, 2))
+        c = tuple(float(v) for v in rng.uniform(0.0, 0.95, 2))
+        lam = tuple(float(v) for v in rng.uniform(0.2, 5.0, 2))
+        if i < n_big:
+            k, n = int(rng.integers(700, 1001)), big_histories
+        else:
+            k, n = int(rng.integers(10, 1001)), int(10 ** rng.uniform(3, 5))
+        specs.append(Spec(3, sig, c, lam, k, n, 7000 + seed * 100 + i, name=f"mix{seed}[{i}]"))
+    return specs
+
+
+def test_fine_mesh_batch_with_tiny_problems_equals_single_runs(cls):
+    """Fine meshes in a batch whose histories sit almost all in chunks of
+    thousands of histories: the launch keeps one LDS tally buffer per wave even
+    though a few problems are tiny (their chunks hold tens of histories). Every
+    problem gets the tallies of its lone run: counts exactly, flux to FP64
+    summation order."""
+    specs = _fine_mesh_mix(160_000_000, 2, 8, seed=1)
+    _print("fine-mesh batch:", [(s.histories, s.nbins) for s in specs])
+    probs = [gpu_problem(s, fp32=True) for s in specs]
+    try:
+        cls.cls_run_batch(probs, [s.histories for s in specs], [s.seed for s in specs])
+        batched = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(probs, specs)]
+        for s, p, (tb, fb, sb) in zip(specs, probs, batched):
+            cls.cls_run(p, s.histories, s.seed)
+            ta, fa, _ = cls.cls_read_tallies(p, s.nbins)
+            _same_results(tallies_dict(ta), fa, tallies_dict(tb), fb, s.name)
+            assert np.all(np.isfinite(sb)), s.name
+    finally:
+        for p in probs:
+            cls.cls_destroy_problem(p)
+
+
+def test_served_rounds_split_big_requests_and_keep_results(cls):
+    """Two big fine-mesh requests and a few tiny ones submitted at once to a
+    default server: a round holds at most ~3 of the largest chunks per wave
+    (~2.4e8 to 3.9e8 histories for these meshes), shared equally between the
+    requests, so each big request (5e8 histories) runs over several rounds
+    while a tiny one finishes in the round it joins; each result equals its
+    lone run (counts exactly, flux to summation order)."""
+    specs = _fine_mesh_mix(500_000_000, 2, 6, seed=2)
+    _print("served mix:", [(s.histories, s.nbins) for s in specs])
+    probs = [gpu_problem(s, fp32=True) for s in specs]
+    srv = cls.cls_server_create()
+    try:
+        tickets = [cls.cls_server_submit(srv, p, s.histories, s.seed) for s, p in zip(specs, probs)]
+        for tk in tickets:
+            assert cls.cls_server_wait(srv, tk, 120.0)
+        infos = [cls.cls_server_request_info(srv, tk) for tk in tickets]
+        stats = cls.cls_server_get_stats(srv)
+        _print("server stats", stats, "rounds per request", [i["rounds"] for i in infos])
+        assert stats["completed"] == len(specs) and stats["failed"] == 0
+        assert all(i["rounds"] > 1 for i in infos[:2])          # big requests over several rounds
+        assert all(i["rounds"] == 1 for i in infos[2:])         # tiny ones in one
+        served = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(probs, specs)]
+    finally:
+        cls.cls_server_destroy(srv)
+    try:
+        for s, p, (tm, fm, _) in zip(specs, probs, served):
+            cls.cls_run(p, s.histories, s.seed)
+            ta, fa, _ = cls.cls_read_tallies(p, s.nbins)
+            _same_results(tallies_dict(ta), fa, tallies_dict(tm), fm, s.name)
+    finally:
+        for p in probs:
+            cls.cls_destroy_problem(p)
+
+
 def test_single_tally_buffer_mode_matches_oracle(cls):
     """A 1000-bin mesh with chunks of at least 2048 histories runs with one LDS
     tally buffer per wave (more waves resident than with two); with chunks of
