@@ -66,18 +66,12 @@ void cache_store(const std::string &key, const cls_launch_config &c)
 extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories, int n,
                                    uint64_t sample_histories, cls_launch_config *best, double *best_rate)
 {
-    if (!problems || !histories || n < 1 || !best) return fail(CLS_ERR_INVALID_ARG, "NULL or empty argument");
-    for (int i = 0; i < n; ++i) {
-        if (!problems[i] || histories[i] == 0) return fail(CLS_ERR_INVALID_ARG, "NULL problem or zero histories");
-        if (!same_variant(variant_of(problems[0]), variant_of(problems[i])))
-            return fail(CLS_ERR_INVALID_ARG, "autotune problems must share geometry, source, estimator and precision");
-    }
-    int max_bins = 1;
+    if (!histories || !best) return fail(CLS_ERR_INVALID_ARG, "NULL argument");
     uint64_t total = 0;
-    for (int i = 0; i < n; ++i) {
-        max_bins = std::max(max_bins, problems[i]->nbins);
-        total += histories[i];
-    }
+    const cls_status chk = check_problem_set(problems, n, histories, &total, "autotune");
+    if (chk != CLS_OK) return chk;
+    int max_bins = 1;
+    for (int i = 0; i < n; ++i) max_bins = std::max(max_bins, problems[i]->nbins);
     const std::string key = cache_key(variant_of(problems[0]), max_bins);
     if (cache_lookup(key, best)) {
         if (best_rate) *best_rate = 0.0;

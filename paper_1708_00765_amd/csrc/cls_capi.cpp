@@ -150,15 +150,15 @@ cls_status ensure_device(cls_problem *p, uint64_t trace_n)
     if (p->device >= 0 && p->device != di.id)
         return fail(CLS_ERR_STATE, "problem was first run on another device");
     p->device = di.id;
-    if (!p->h_prob) {
-        HIP_TRY(hipHostMalloc((void **)&p->h_prob, sizeof(DevProblem), hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc((void **)&p->h_items, 4 * sizeof(uint64_t), hipHostMallocDefault));
+    // each piece on its own, so that a call after a failed one completes the set
+    if (!p->h_prob) HIP_TRY(hipHostMalloc((void **)&p->h_prob, sizeof(DevProblem), hipHostMallocDefault));
+    if (!p->h_items) HIP_TRY(hipHostMalloc((void **)&p->h_items, 4 * sizeof(uint64_t), hipHostMallocDefault));
+    if (!p->h_record)
         HIP_TRY(hipHostMalloc((void **)&p->h_record, record_words(p->nbins) * sizeof(uint64_t),
                               hipHostMallocDefault));
-        HIP_TRY(hipEventCreate(&p->ev_k0));
-        HIP_TRY(hipEventCreate(&p->ev_k1));
-        HIP_TRY(hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming));
-    }
+    if (!p->ev_k0) HIP_TRY(hipEventCreate(&p->ev_k0));
+    if (!p->ev_k1) HIP_TRY(hipEventCreate(&p->ev_k1));
+    if (!p->ev_done) HIP_TRY(hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming));
     const size_t need = workspace_bytes(p->nbins, trace_n);
     if (p->dev && p->dev_bytes >= need) {
         if (trace_n > p->trace_cap || p->trace_cap == 0) carve(p, trace_n);
@@ -250,6 +250,32 @@ uint64_t trace_count(const cls_problem *p, uint64_t histories)
 bool same_variant(const Variant &a, const Variant &b)
 {
     return a.geom == b.geom && a.est == b.est && a.src == b.src && a.fp32 == b.fp32 && a.trace == b.trace;
+}
+
+cls_status check_problem_set(cls_problem *const *problems, int n, const uint64_t *histories,
+                             uint64_t *total, const char *what)
+{
+    if (!problems || n < 1) return fail(CLS_ERR_INVALID_ARG, "empty or NULL problem list");
+    for (int i = 0; i < n; ++i) {
+        if (!problems[i]) return fail(CLS_ERR_INVALID_ARG, "NULL problem in the list");
+        if (!same_variant(variant_of(problems[0]), variant_of(problems[i])))
+            return fail(CLS_ERR_INVALID_ARG, std::string(what) +
+                                                 " problems must share geometry, source, estimator and precision");
+    }
+    std::vector<cls_problem *> sorted(problems, problems + n);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fail(CLS_ERR_INVALID_ARG, "a problem appears twice in the list");
+    if (histories) {
+        uint64_t sum = 0;
+        for (int i = 0; i < n; ++i) {
+            if (histories[i] == 0) return fail(CLS_ERR_INVALID_ARG, "histories must be >= 1");
+            if (histories[i] > UINT64_MAX - sum) return fail(CLS_ERR_INVALID_ARG, "total histories exceed 2^64 - 1");
+            sum += histories[i];
+        }
+        if (total) *total = sum;
+    }
+    return CLS_OK;
 }
 
 Variant variant_of(const cls_problem *p)
@@ -655,10 +681,11 @@ cls_status batch_space(int device, size_t bytes, BatchSpace **out)
         g_batch.emplace_back();
         bs = &g_batch.back();
         bs->device = device;
-        HIP_TRY(hipEventCreate(&bs->k0));
-        HIP_TRY(hipEventCreate(&bs->k1));
-        HIP_TRY(hipEventCreateWithFlags(&bs->done, hipEventDisableTiming));
     }
+    // each event on its own, so that a call after a failed one completes the set
+    if (!bs->k0) HIP_TRY(hipEventCreate(&bs->k0));
+    if (!bs->k1) HIP_TRY(hipEventCreate(&bs->k1));
+    if (!bs->done) HIP_TRY(hipEventCreateWithFlags(&bs->done, hipEventDisableTiming));
     if (bs->dev_bytes < bytes) {
         if (bs->dev) (void)hipFree(bs->dev);
         if (bs->host) (void)hipHostFree(bs->host);
@@ -681,24 +708,17 @@ cls_status batch_space(int device, size_t bytes, BatchSpace **out)
 extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t *histories,
                                     const uint64_t *seeds, int n)
 {
-    if (!problems || !histories || !seeds || n < 1) return fail(CLS_ERR_INVALID_ARG, "empty or NULL batch");
-    for (int i = 0; i < n; ++i) {
-        if (!problems[i]) return fail(CLS_ERR_INVALID_ARG, "NULL problem in batch");
-        if (histories[i] == 0) return fail(CLS_ERR_INVALID_ARG, "histories must be >= 1");
-        if (!same_variant(variant_of(problems[0]), variant_of(problems[i])))
-            return fail(CLS_ERR_INVALID_ARG, "batch problems must share geometry, source, estimator and precision");
-        for (int j = 0; j < i; ++j)
-            if (problems[j] == problems[i]) return fail(CLS_ERR_INVALID_ARG, "a problem appears twice in the batch");
-    }
+    if (!histories || !seeds) return fail(CLS_ERR_INVALID_ARG, "NULL histories or seeds");
+    uint64_t total_hist = 0;
+    cls_status st = check_problem_set(problems, n, histories, &total_hist, "batch");
+    if (st != CLS_OK) return st;
     std::lock_guard<std::mutex> lk(g_batch_mu);
     int max_bins = 1;
     size_t rec_words = 0;
-    uint64_t total_hist = 0;
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
-        total_hist += histories[i];
         const uint64_t tn = trace_count(p, histories[i]);
-        cls_status st = ensure_device(p, tn);
+        st = ensure_device(p, tn);
         if (st != CLS_OK) return st;
         if (tn > p->trace_cap) return fail(CLS_ERR_INVALID_ARG, "bound device memory too small for the trace");
         if (p->has_run) HIP_TRY(hipEventSynchronize(p->ev_done));
@@ -706,7 +726,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
         rec_words += record_words(p->nbins);
     }
     DeviceInfo di;
-    cls_status st = device_info(&di);
+    st = device_info(&di);
     if (st != CLS_OK) return st;
     int grid, block, stride;
     size_t lds;

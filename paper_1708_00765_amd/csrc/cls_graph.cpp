@@ -89,17 +89,12 @@ cls_status cls_batch_create(cls_problem *const *problems, int n, cls_batch **out
 {
     if (!out) return fail(CLS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (!problems || n < 1) return fail(CLS_ERR_INVALID_ARG, "empty or NULL batch");
-    for (int i = 0; i < n; ++i) {
-        if (!problems[i]) return fail(CLS_ERR_INVALID_ARG, "NULL problem in batch");
+    cls_status st = check_problem_set(problems, n, nullptr, nullptr, "batch");
+    if (st != CLS_OK) return st;
+    for (int i = 0; i < n; ++i)
         if (problems[i]->flags & CLS_F_TRACE) return fail(CLS_ERR_INVALID_ARG, "graph batches do not record traces");
-        if (!same_variant(variant_of(problems[0]), variant_of(problems[i])))
-            return fail(CLS_ERR_INVALID_ARG, "batch problems must share geometry, source, estimator and precision");
-        for (int j = 0; j < i; ++j)
-            if (problems[j] == problems[i]) return fail(CLS_ERR_INVALID_ARG, "a problem appears twice in the batch");
-    }
     DeviceInfo di;
-    cls_status st = device_info(&di);
+    st = device_info(&di);
     if (st != CLS_OK) return st;
     cls_batch *b = new (std::nothrow) cls_batch();
     if (!b) return fail(CLS_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -134,8 +129,9 @@ cls_status cls_batch_run(cls_batch *b, const uint64_t *histories, const uint64_t
 {
     if (!b || !histories || !seeds) return fail(CLS_ERR_INVALID_ARG, "NULL argument");
     const int n = (int)b->probs.size();
-    for (int i = 0; i < n; ++i)
-        if (histories[i] == 0) return fail(CLS_ERR_INVALID_ARG, "histories must be >= 1");
+    uint64_t total = 0;
+    const cls_status chk = check_problem_set(b->probs.data(), n, histories, &total, "batch");
+    if (chk != CLS_OK) return chk;
     for (cls_problem *p : b->probs)
         if (p->has_run) HIP_TRY(hipEventSynchronize(p->ev_done));
     DevProblem *h_probs = (DevProblem *)b->host;
@@ -144,8 +140,6 @@ cls_status cls_batch_run(cls_batch *b, const uint64_t *histories, const uint64_t
     uint64_t *d_rec = (uint64_t *)(b->dev + b->probs_bytes + b->items_bytes);
     h_items[0] = 0;
     size_t off = 0;
-    uint64_t total = 0;
-    for (int i = 0; i < n; ++i) total += histories[i];
     if (!b->exec) {
         // launch shape for the history counts of this (first) run
         DeviceInfo di;

@@ -88,6 +88,11 @@ void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, u
                       uint64_t trace_n, DevProblem *out);
 Variant variant_of(const cls_problem *p);
 bool same_variant(const Variant &a, const Variant &b);
+// Arguments of a launch over several problems: no NULL problem, one kernel
+// variant, no problem twice; when histories is given, every count >= 1 and
+// their sum (stored in *total) below 2^64. `what` names the caller's rule.
+cls_status check_problem_set(cls_problem *const *problems, int n, const uint64_t *histories,
+                             uint64_t *total, const char *what);
 // One LDS tally buffer per wave (instead of two) doubles the waves an LDS-bound
 // launch keeps resident, but a wave then waits for the last histories of its
 // chunk before it claims the next; that wait pays only for chunks of at least

@@ -135,6 +135,19 @@ def test_batch_argument_validation(cls):
             cls.cls_run_batch([a, a], [10, 10], [1, 2])
         with pytest.raises(cls.ClsError):                 # zero histories
             cls.cls_run_batch([a], [0], [1])
+        c = cls.cls_create_problem(3, 10.0, (0.5, 1.0), (0.2, 0.9), (1.0, 0.3))
+        try:
+            # argument errors come before any device work, with or without a GPU
+            for call in (lambda: cls.cls_run_batch([a, c], [2**63, 2**63], [1, 2]),   # total overflows
+                         lambda: cls.cls_autotune([a, c], [2**63, 2**63]),
+                         lambda: cls.cls_batch_create([a, a]),
+                         lambda: cls.cls_batch_create([a, b]),
+                         lambda: cls.cls_autotune([c, a, c], [10, 10, 10])):
+                with pytest.raises(cls.ClsError) as ei:
+                    call()
+                assert ei.value.status == cls.CLS_ERR_INVALID_ARG
+        finally:
+            cls.cls_destroy_problem(c)
     finally:
         cls.cls_destroy_problem(a)
         cls.cls_destroy_problem(b)
