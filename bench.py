@@ -387,8 +387,10 @@ def run_served_saturated(cls, rate, seconds):
         cls.cls_server_destroy(srv)
     try:
         slots = 0.0
+        flights = 0
         for p, s in zip(probs, specs):
             t, _, _ = cls.cls_read_tallies(p, s.nbins)
+            flights += t.flights
             slots += perf_model.algorithmic_slots(s.geom_name, t.histories, t.flights, t.scatters,
                                                   t.lateral_reflections, fp32=True, track=not s.collision)
     finally:
@@ -399,7 +401,7 @@ def run_served_saturated(cls, rate, seconds):
     achieved = slots / span / 1e12
     peak = perf_model.PEAK_SLOTS_PER_S / 1e12
     return {"requests": len(specs), "completed": stats["completed"], "failed": stats["failed"],
-            "histories": hist, "seconds": span, "value": hist / span, "unit": "histories/s",
+            "histories": hist, "flights": flights, "seconds": span, "value": hist / span, "unit": "histories/s",
             "rounds": stats["rounds"],
             "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
                          "frac": achieved / peak, "algorithmic_slots": slots},

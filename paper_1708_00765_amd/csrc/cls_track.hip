@@ -197,10 +197,18 @@ struct Lane {
     R iux, aiuy, aiuz, ig;   // 1/u_x, |1/u_y|, |1/u_z|, 1/(chord factor)
     R fx;                    // x inside its flux bin, in bin widths (FP32 track-length)
     double tscore;           // this history's flux score
+    // Sums over the lane's histories in chunk slot `slot` (the current one
+    // included): flux score and its square per history, interface crossings,
+    // scatters, lateral reflections and the outcomes. They move to the slot's
+    // LDS counters only when the lane changes slot or the slot is flushed, so
+    // that a history's end costs no LDS atomics (all ending lanes would hit
+    // the same addresses).
+    double ssum, ssq;
     uint64_t h;
     uint64_t hash;
     uint32_t step;
-    uint32_t n_int, n_scat, n_lat;   // this history's interface crossings, scatters, lateral reflections
+    uint32_t n_int, n_scat, n_lat;
+    uint32_t n_t, n_r, n_a, n_cap;
     int m, slot, pid, kcur;  // material, chunk slot, problem, bin of x
     int tb;                  // offset of the slot's LDS tally buffer (doubles)
     bool alive;
@@ -465,6 +473,30 @@ struct SlotState {
     int32_t pid, open;
 };
 
+// Move a lane's sums to the LDS counters of its slot (a lane that finished no
+// history there holds none) and clear them.
+template <typename R>
+__device__ __forceinline__ void lane_to_slot(Lane<R> &L, double *wsum, uint32_t *wctr)
+{
+    if ((L.n_t | L.n_r | L.n_a | L.n_cap) != 0u) {
+        double *ss = wsum + 2 * L.slot;
+        lds_add(ss, L.ssum);
+        lds_add(ss + 1, L.ssq);
+        uint32_t *c = wctr + L.slot * kSlotCounters;
+        atomicAdd(c + S_T, L.n_t);
+        atomicAdd(c + S_R, L.n_r);
+        atomicAdd(c + S_A, L.n_a);
+        atomicAdd(c + S_CAP, L.n_cap);
+        atomicAdd(c + S_SCAT, L.n_scat);
+        atomicAdd(c + S_INT, L.n_int);
+        atomicAdd(c + S_LAT, L.n_lat);
+    }
+    L.ssum = 0.0;
+    L.ssq = 0.0;
+    L.n_t = L.n_r = L.n_a = L.n_cap = 0u;
+    L.n_int = L.n_scat = L.n_lat = 0u;
+}
+
 // Move a finished chunk's tallies from its LDS slot to HBM: the flux bins
 // (prefix-scanned first for the difference-form track-length tally) as the
 // chunk's batch sum S and its square over the chunk size Q, the history score
@@ -494,8 +526,14 @@ __device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, dou
     }
     const double st = ssum[0];
     const double st2 = ssum[1];
-    // one counter per lane: lanes 0..S_NCTR-1 move them to HBM
-    const uint32_t cv = lane < S_NCTR ? c[lane] : 0u;
+    // one counter per lane: lanes 0..S_NCTR-1 move them to HBM. Flights and
+    // collisions are derived: a flight ends in a leak (T, R), an absorption, a
+    // scatter, an interface crossing or a lateral mirror (a capped history's
+    // refused step is no flight); a collision is a scatter or an absorption.
+    uint64_t cv = lane < S_NCTR ? c[lane] : 0u;
+    const uint64_t n_t = c[S_T], n_r = c[S_R], n_a = c[S_A], n_sc = c[S_SCAT], n_in = c[S_INT], n_la = c[S_LAT];
+    if (lane == S_FLIGHTS) cv = n_t + n_r + n_a + n_sc + n_in + n_la;
+    if (lane == S_COLL) cv = n_sc + n_a;
     if (lane < S_NCTR) c[lane] = 0u;
     const int slot_ctr_to_global[S_NCTR] = {C_TRANSMITTED, C_REFLECTED, C_ABSORBED, C_CAPPED, C_FLIGHTS,
                                             C_COLLISIONS, C_SCATTERS, C_INTERFACES, C_LATERAL};
@@ -548,8 +586,9 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     Lane<R> L;
     L.x = 0.0; L.dy = L.dz = L.ux = L.uy = L.uz = 0;
     L.iux = L.aiuy = L.aiuz = 0; L.ig = 1; L.fx = 0;
-    L.tscore = 0.0; L.h = 0; L.hash = 0; L.step = 0;
+    L.tscore = 0.0; L.ssum = 0.0; L.ssq = 0.0; L.h = 0; L.hash = 0; L.step = 0;
     L.n_int = L.n_scat = L.n_lat = 0;
+    L.n_t = L.n_r = L.n_a = L.n_cap = 0;
     L.m = 0; L.slot = 0; L.pid = 0; L.kcur = 0; L.tb = 0; L.alive = false;
 
     for (;;) {
@@ -609,14 +648,13 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                 // lanes' registers, where selects would first copy them)
                 const bool nw = !L.alive && r < take;
                 if (nw) {
+                    // sums of the lane's histories in the other slot go there first
+                    if (L.slot != cp) lane_to_slot(L, wsum, wctr);
                     L.slot = cp;
                     L.tb = cp * KP;
                     L.pid = C.pid;
                     L.h = C.h0 + C.next + r;
                     L.step = 0u;
-                    L.n_int = 0u;
-                    L.n_scat = 0u;
-                    L.n_lat = 0u;
                     L.tscore = 0.0;
                     if (TRACE) L.hash = 0xCBF29CE484222325ull;
                     L.alive = true;
@@ -656,37 +694,35 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             C.live -= popc(in_c);
             O.live -= popc(m_fin & ~in_c);
             if (fin) {
-                double *ss = wsum + 2 * L.slot;
-                lds_add(ss, L.tscore);
-                lds_add(ss + 1, L.tscore * L.tscore);
-                uint32_t *c = wctr + L.slot * kSlotCounters;
-                // leak at x = L, leak at x = 0, absorption -> T, R, A (consecutive
-                // event codes in reverse order), the cap -> CAP
-                const int outcome = ev == EV_CAP ? S_CAP : EV_LEAK_XHI - ev;
-                atomicAdd(c + outcome, 1u);
-                // steps = source + flights (+ the refused step of a capped history)
-                const uint32_t flights = L.step - 1u - (ev == EV_CAP ? 1u : 0u);
-                atomicAdd(c + S_FLIGHTS, flights);
-                atomicAdd(c + S_COLL, L.n_scat + (ev == EV_ABSORB ? 1u : 0u));
-                atomicAdd(c + S_SCAT, L.n_scat);
-                atomicAdd(c + S_INT, L.n_int);
-                if (G == GEOM_EXT2D || G == GEOM_CUBE3D) atomicAdd(c + S_LAT, L.n_lat);
+                L.ssum += L.tscore;
+                L.ssq = fma(L.tscore, L.tscore, L.ssq);
+                L.n_t += ev == EV_LEAK_XHI ? 1u : 0u;
+                L.n_r += ev == EV_LEAK_XLO ? 1u : 0u;
+                L.n_a += ev == EV_ABSORB ? 1u : 0u;
+                L.n_cap += ev == EV_CAP ? 1u : 0u;
                 if (TRACE) {
                     const DevProblem &P = A.probs[L.pid];
                     if (L.h < P.trace_n) {
+                        // steps = source + flights (+ the refused step of a capped history)
                         P.trace_hash[L.h] = L.hash;
-                        P.trace_len[L.h] = flights;
+                        P.trace_len[L.h] = L.step - 1u - (ev == EV_CAP ? 1u : 0u);
                     }
                 }
                 L.alive = false;
             }
 
             // ------------- flush chunks whose last history ended -------------
-            if (C.open && C.next == C.cnt && C.live == 0)
+            // (every lane that ran histories of the chunk is idle now and holds
+            // their sums; they join the slot's counters first)
+            if (C.open && C.next == C.cnt && C.live == 0) {
+                if (L.slot == cp) lane_to_slot(L, wsum, wctr);
                 flush_slot<EST>(C, A, wbuf + cp * KP, wsum + 2 * cp, wctr + cp * kSlotCounters, lane);
-            if (O.open && O.next == O.cnt && O.live == 0)
+            }
+            if (O.open && O.next == O.cnt && O.live == 0) {
+                if (L.slot == (cp ^ 1)) lane_to_slot(L, wsum, wctr);
                 flush_slot<EST>(O, A, wbuf + (cp ^ 1) * KP, wsum + 2 * (cp ^ 1), wctr + (cp ^ 1) * kSlotCounters,
                                 lane);
+            }
         }
     }
 }
