@@ -306,7 +306,7 @@ def run_ext2d_comparison(cls, torch, stream, steps):
         # default launch configuration, then the autotuner's choice for these sets
         # (timed before and after the tuned runs: the order is not what differs)
         w_default = time_batched()
-        cfg, tuned_rate = cls.cls_autotune(p32, hist, sample_histories=20_000_000)
+        cfg, tuned_rate = cls.cls_autotune(p32, hist)
         w32 = time_batched()
         cls.cls_set_launch_config(0, 0, 0, 0)         # the FP64 plain runs use the defaults
         w_default = min(w_default, time_batched())

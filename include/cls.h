@@ -220,9 +220,11 @@ cls_status cls_set_launch_config(const cls_launch_config *cfg);
 cls_status cls_get_launch_config(cls_launch_config *cfg);
 
 /* Autotuner: time candidate launch shapes (workgroup size, chunk size, refill
- * threshold) on a calibration sample of about sample_histories histories (0:
- * 2e7) drawn from `problems` (same rules as cls_run_batch) run as one batched
- * launch, make the fastest the process-wide launch configuration and return it
+ * threshold) on a calibration part of about sample_histories histories (0: a
+ * quarter of the summed histories, at least 2e7) of the batch cls_run_batch
+ * would run for `problems` and `histories` (same rules): the first chunks of
+ * every problem, cut as in the whole batch. Makes the fastest shape the
+ * process-wide launch configuration and returns it
  * in *best (and its rate in histories/s in *best_rate, 0 when it came from the
  * cache). When the environment variable CLS_AUTOTUNE_CACHE names a file,
  * results are cached there per device, kernel variant and mesh-size class.

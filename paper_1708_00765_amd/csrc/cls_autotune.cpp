@@ -77,16 +77,15 @@ extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t 
         if (best_rate) *best_rate = 0.0;
         return cls_set_launch_config(best);
     }
-    // calibration sample: every problem scaled by the same factor, at least 64 histories
-    if (sample_histories == 0) sample_histories = 20000000ull;
-    const double scale = std::min(1.0, (double)sample_histories / (double)total);
-    std::vector<uint64_t> h(n), seeds(n);
-    uint64_t sample_total = 0;
-    for (int i = 0; i < n; ++i) {
-        h[i] = std::max<uint64_t>(std::min<uint64_t>(64, histories[i]), (uint64_t)(scale * (double)histories[i]));
-        seeds[i] = 0x5DEECE66Dull * (uint64_t)(i + 1);
-        sample_total += h[i];
-    }
+    // Calibration: a part of the real batch, the first chunks of every problem
+    // cut exactly as the whole batch would be (same launch shape, chunk sizes and
+    // one-or-two LDS buffer choice; a batch of scaled-down history counts has
+    // smaller chunks and can favour shapes that the whole run does not). By
+    // default a quarter of the work, at least 2e7 histories.
+    if (sample_histories == 0) sample_histories = std::max<uint64_t>(20000000ull, total / 4);
+    const double fraction = std::min(1.0, (double)sample_histories / (double)total);
+    std::vector<uint64_t> seeds(n);
+    for (int i = 0; i < n; ++i) seeds[i] = 0x5DEECE66Dull * (uint64_t)(i + 1);
     cls_launch_config saved;
     cls_status st = cls_get_launch_config(&saved);
     if (st != CLS_OK) return st;
@@ -102,8 +101,9 @@ extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t 
                 st = cls_set_launch_config(&cfg);
                 if (st != CLS_OK) return st;
                 double ms = 1e30;
+                uint64_t processed = 0;
                 for (int rep = 0; rep < 2; ++rep) {
-                    st = cls_run_batch(problems, h.data(), seeds.data(), n);
+                    st = run_batch_part(problems, histories, seeds.data(), n, fraction, &processed);
                     if (st != CLS_OK && st != CLS_ERR_EVENT_CAP) {
                         (void)cls_set_launch_config(&saved);
                         return st;
@@ -112,7 +112,7 @@ extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t 
                     (void)cls_read_tallies(problems[0], &t, nullptr, nullptr, 0);
                     ms = std::min(ms, t.track_ms);
                 }
-                const double rate = (double)sample_total / (ms * 1e-3);
+                const double rate = (double)processed / (ms * 1e-3);
                 if (rate > best_r) {
                     best_r = rate;
                     best_c = cfg;

@@ -705,8 +705,11 @@ cls_status batch_space(int device, size_t bytes, BatchSpace **out)
 
 }  // namespace
 
-extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t *histories,
-                                    const uint64_t *seeds, int n)
+namespace cls {
+namespace rt {
+
+cls_status run_batch_part(cls_problem *const *problems, const uint64_t *histories, const uint64_t *seeds, int n,
+                          double fraction, uint64_t *processed)
 {
     if (!histories || !seeds) return fail(CLS_ERR_INVALID_ARG, "NULL histories or seeds");
     uint64_t total_hist = 0;
@@ -754,6 +757,7 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
     uint64_t *d_items = (uint64_t *)(bs->dev + probs_bytes);
     uint64_t *d_rec = (uint64_t *)(bs->dev + probs_bytes + items_bytes);
     const uint64_t waves_total = (uint64_t)grid * (uint64_t)(block / 64);
+    uint64_t done_hist = 0;
     h_items[0] = 0;
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
@@ -763,7 +767,13 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
         fill_dev_problem(p, histories[i], seeds[i], chunk, tn, &h_probs[i]);
         h_probs[i].record = d_rec + off;
         off += record_words(p->nbins);
-        h_items[i + 1] = h_items[i] + (histories[i] + chunk - 1) / chunk;
+        const uint64_t items = (histories[i] + chunk - 1) / chunk;
+        // a part of the run: its first chunks, cut exactly as in the whole run
+        const uint64_t take = fraction >= 1.0
+                                  ? items
+                                  : std::min(items, std::max<uint64_t>(1, (uint64_t)std::ceil(fraction * (double)items)));
+        h_items[i + 1] = h_items[i] + take;
+        done_hist += std::min(histories[i], take * chunk);
     }
     h_items[n + 1] = 0;   // queue head
     hipStream_t s = problems[0]->stream;
@@ -803,6 +813,16 @@ extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t
         p->trace_n = h_probs[i].trace_n;
         capped = capped || p->h_record[C_CAPPED] != 0;
     }
+    if (processed) *processed = done_hist;
     if (capped) return fail(CLS_ERR_EVENT_CAP, "a history reached the flight cap");
     return CLS_OK;
+}
+
+}  // namespace rt
+}  // namespace cls
+
+extern "C" cls_status cls_run_batch(cls_problem *const *problems, const uint64_t *histories,
+                                    const uint64_t *seeds, int n)
+{
+    return run_batch_part(problems, histories, seeds, n, 1.0, nullptr);
 }

@@ -107,6 +107,13 @@ using SmallShareFn = std::function<double(uint64_t waves_total, uint64_t max_chu
 cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *grid, int *block,
                      size_t *lds, int *lds_stride, LaunchShape *used,
                      const SmallShareFn &small_share = SmallShareFn());
+// cls_run_batch, or a part of it: with fraction < 1 each problem runs only the
+// first ceil(fraction x its chunks) chunks (at least one), cut and launched
+// exactly as in the whole batch (same launch shape, chunk sizes and batch
+// totals); *processed (may be NULL) receives the histories run. The problems'
+// results are then those of the part (autotuner calibration).
+cls_status run_batch_part(cls_problem *const *problems, const uint64_t *histories, const uint64_t *seeds, int n,
+                          double fraction, uint64_t *processed);
 void quenched_release(cls_problem *p);
 
 }  // namespace rt

@@ -168,9 +168,14 @@ def test_graph_replays_match_eager_runs(cls):
             cls.cls_destroy_problem(p)
 
 
-def test_results_do_not_depend_on_launch_shape_and_autotune(cls):
+@pytest.mark.parametrize("fp32", [True, False])
+def test_results_do_not_depend_on_launch_shape_and_autotune(cls, fp32):
+    """Counts exactly, score and flux sums to FP64 summation order, for launch
+    shapes from one-wave workgroups with 64-history chunks refilled lane by
+    lane (a lane changes chunk slot after almost every history) to 65536-history
+    chunks; then the autotuner's choice (FP32)."""
     specs = workload("cube3d_track", histories=300_000)[:4]
-    probs = [gpu_problem(s, fp32=True) for s in specs]
+    probs = [gpu_problem(s, fp32=fp32) for s in specs]
     hist = [s.histories for s in specs]
     seeds = [s.seed for s in specs]
     try:
@@ -184,8 +189,12 @@ def test_results_do_not_depend_on_launch_shape_and_autotune(cls):
                 # counts are exact; the flux sums only change by atomic ordering
                 for k in COUNTS:
                     assert getattr(t0, k) == getattr(t1, k), (cfg, k)
+                for k in ("total_flux", "sigma_total_flux"):
+                    assert abs(getattr(t0, k) - getattr(t1, k)) <= 1e-11 * abs(getattr(t0, k)), (cfg, k)
                 np.testing.assert_allclose(f0, f1, rtol=1e-11, atol=1e-13)
         cls.cls_set_launch_config(0, 0, 0, 0)
+        if not fp32:
+            return
         cfg, rate = cls.cls_autotune(probs, hist, sample_histories=2_000_000)
         _print("autotuned", cfg, rate)
         assert cfg["waves_per_block"] in (0, 1, 2, 4, 8) and rate > 0
