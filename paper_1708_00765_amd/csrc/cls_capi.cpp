@@ -61,8 +61,6 @@ constexpr int kDefaultMaxChunk = 16384;
 constexpr uint64_t kDefaultMaxSteps = 100000000ull;
 constexpr size_t kLdsLimit = 65536;
 constexpr int kDefaultRefillMin = 4;
-// chunks (batches of the flux error) a problem of a batch keeps at least
-constexpr uint64_t kMinErrorBatches = 256;
 }  // namespace
 
 namespace cls {
@@ -175,33 +173,6 @@ cls_status ensure_device(cls_problem *p, uint64_t trace_n)
     p->dev_owned = true;
     carve(p, trace_n);
     return CLS_OK;
-}
-
-uint64_t chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk)
-{
-    uint64_t c = (n + 4 * waves_total - 1) / (4 * waves_total);
-    c = std::max<uint64_t>(c, 256);
-    if (n / c < waves_total) c = std::max<uint64_t>(64, (n + waves_total - 1) / waves_total);
-    c = std::min<uint64_t>(c, max_chunk);
-    return std::max<uint64_t>(c, 1);
-}
-
-// Run together with other problems, a small problem need not be cut into a
-// chunk per wave (which, with fine meshes, makes the chunk flushes the
-// dominant cost): its chunks grow up to `cap`, while it keeps at least 256
-// chunks, the batches of its flux error, when its history count allows.
-uint64_t grouped_chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk, uint64_t cap)
-{
-    const uint64_t c = chunk_size(n, waves_total, max_chunk);
-    const uint64_t c_err = (n + kMinErrorBatches - 1) / kMinErrorBatches;
-    return std::max(c, std::min(std::min(cap, c_err), max_chunk));
-}
-
-// A batch: chunks up to the size that gives the whole batch about 32 chunks
-// per wave (the density a single large problem gets).
-uint64_t batch_chunk_size(uint64_t n, uint64_t total, uint64_t waves_total, uint64_t max_chunk)
-{
-    return grouped_chunk_size(n, waves_total, max_chunk, (total + 32 * waves_total - 1) / (32 * waves_total));
 }
 
 void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,

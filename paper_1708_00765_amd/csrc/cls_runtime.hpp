@@ -11,6 +11,7 @@
 
 #include "cls.h"
 #include "cls_internal.hpp"
+#include "cls_sched.hpp"
 
 struct QuenchedState;   // quenched-disorder workspace (cls_quenched_api.cpp)
 
@@ -77,13 +78,9 @@ size_t align256(size_t v);
 size_t workspace_bytes(int nbins, uint64_t trace_n);
 cls_status ensure_device(cls_problem *p, uint64_t trace_n);
 uint64_t trace_count(const cls_problem *p, uint64_t histories);
-uint64_t chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk);
-// Chunk of one problem run together with others (which fill the GPU): at most
-// `cap` histories, and at least 256 chunks when n allows (never below
-// chunk_size).
-uint64_t grouped_chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk, uint64_t cap);
-// Chunk of one problem of a batch whose problems hold `total` histories.
-uint64_t batch_chunk_size(uint64_t n, uint64_t total, uint64_t waves_total, uint64_t max_chunk);
+using sched::batch_chunk_size;
+using sched::chunk_size;
+using sched::grouped_chunk_size;
 void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,
                       uint64_t trace_n, DevProblem *out);
 Variant variant_of(const cls_problem *p);

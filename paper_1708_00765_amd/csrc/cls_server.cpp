@@ -39,9 +39,6 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Chunks of the largest size per wave that a round holds at least.
-constexpr double kRoundChunksPerWave = 3.0;
-
 enum ReqState { RQ_PENDING, RQ_ACTIVE, RQ_FINALIZING, RQ_DONE, RQ_FAILED };
 
 struct Request {
@@ -211,36 +208,16 @@ bool launch_round(cls_server *s, RoundSlot &sl, cls_status *err)
     const double backlog_share = small_share_of(sl.parts);
     *err = shape_for(v, max_bins, s->di, &grid, &block, &lds, &stride, &used,
                      [backlog_share](uint64_t, uint64_t) { return backlog_share; });
-    // Round size: at least round_histories, and enough for kRoundChunksPerWave
-    // of the largest chunks per wave (a round lasts at least as long as its
-    // largest chunk takes one wave, so smaller rounds leave most waves idle).
+    // Round size (sched::round_budget), shared by water-filling: requests with
+    // less left than an equal share finish in this round, the others get the
+    // equal share of what remains (at least one chunk each).
     const uint64_t waves = *err == CLS_OK ? (uint64_t)grid * (uint64_t)(block / 64) : 1;
-    const double budget = std::max((double)s->cfg.round_histories,
-                                   (double)kRoundChunksPerWave * (double)waves * (double)max_chunk);
-    // Water-filling: requests with less left than an equal share finish in
-    // this round; the others get the equal share of what remains (at least
-    // one chunk each).
-    std::vector<Request *> by_left = reqs;
-    auto left = [](const Request *r) { return (double)(r->n_chunks - r->next_chunk) * (double)r->chunk; };
-    std::sort(by_left.begin(), by_left.end(), [&](const Request *a, const Request *b) { return left(a) < left(b); });
-    double rest = budget, level = 0.0;
-    size_t i_full = 0;
-    for (; i_full < by_left.size(); ++i_full) {
-        const double share = rest / (double)(by_left.size() - i_full);
-        if (left(by_left[i_full]) > share) {
-            level = share;
-            break;
-        }
-        rest -= left(by_left[i_full]);
-    }
+    const double budget = sched::round_budget((double)s->cfg.round_histories, waves, max_chunk);
+    std::vector<sched::RoundClaim> claims;
+    for (Request *r : reqs) claims.push_back({r->chunk, r->n_chunks - r->next_chunk});
+    const std::vector<uint64_t> take = sched::water_fill(claims, budget);
     sl.parts.clear();
-    for (size_t i = 0; i < by_left.size(); ++i) {
-        Request *r = by_left[i];
-        const uint64_t rem = r->n_chunks - r->next_chunk;
-        const uint64_t take = i < i_full ? rem
-                                         : std::min(rem, std::max<uint64_t>(1, (uint64_t)(level / (double)r->chunk)));
-        sl.parts.push_back({r, take});
-    }
+    for (size_t i = 0; i < reqs.size(); ++i) sl.parts.push_back({reqs[i], take[i]});
     // largest chunks first: the work queue hands items out in order, so the
     // small chunks fill the waves that finish early
     std::stable_sort(sl.parts.begin(), sl.parts.end(),
