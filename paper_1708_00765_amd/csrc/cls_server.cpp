@@ -27,6 +27,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -80,6 +81,7 @@ struct cls_server {
     bool stop = false;
     std::deque<Request *> pending;
     std::vector<Request *> active;       // admitted, not yet done
+    std::set<const cls_problem *> in_flight;   // problems with a request being submitted, pending or active
     std::map<uint64_t, Request *> all;
     uint64_t next_ticket = 1;
     size_t in_use = 0, peak = 0;
@@ -113,6 +115,7 @@ void finish(cls_server *s, Request *r, cls_status err)
         ++s->failed;
     }
     s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+    s->in_flight.erase(r->p);
     s->cv_done.notify_all();
 }
 
@@ -430,16 +433,26 @@ cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, 
             delete r;
             return fail(CLS_ERR_STATE, "server is shutting down");
         }
-        for (Request *q : s->active)
-            if (q->p == p) {
-                delete r;
-                return fail(CLS_ERR_STATE, "this problem already has a request in flight");
-            }
-        for (Request *q : s->pending)
-            if (q->p == p) {
-                delete r;
-                return fail(CLS_ERR_STATE, "this problem already has a request in flight");
-            }
+        if (!s->in_flight.insert(p).second) {
+            delete r;
+            return fail(CLS_ERR_STATE, "this problem already has a request in flight");
+        }
+    }
+    // The problem's device memory is allocated here, in the caller's thread
+    // (when it runs on the server's device), so that the worker does not stall
+    // the rounds on allocations; no other request of this problem can be in
+    // the server now.
+    int dev = -1;
+    cls_status st = CLS_OK;
+    if (hipGetDevice(&dev) == hipSuccess && dev == s->device) st = ensure_device(p, 0);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (st == CLS_OK && s->stop) st = fail(CLS_ERR_STATE, "server is shutting down");
+        if (st != CLS_OK) {
+            s->in_flight.erase(p);
+            delete r;
+            return st;
+        }
         r->ticket = s->next_ticket++;
         r->stream = (int)(r->ticket & 1);
         s->all[r->ticket] = r;
