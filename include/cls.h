@@ -274,7 +274,10 @@ typedef struct {
 /* cfg may be NULL (all defaults). Errors: CLS_ERR_NO_DEVICE, CLS_ERR_DEVICE. */
 cls_status cls_server_create(const cls_server_config *cfg, cls_server **out);
 /* Queue a run of p (not CLS_F_TRACE; one request per problem at a time; the
- * problem must not be used otherwise until the request is done). */
+ * problem must not be used otherwise until the request is done). When the
+ * calling thread's current device is the server's, the problem's device
+ * memory is allocated by this call (CLS_ERR_OUT_OF_MEMORY, CLS_ERR_DEVICE),
+ * not by the worker. */
 cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, uint64_t seed,
                              uint64_t *ticket);
 /* CLS_OK when done (read results with cls_read_tallies on the problem),
