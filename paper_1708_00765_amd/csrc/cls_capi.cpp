@@ -691,7 +691,8 @@ cls_status run_batch_part(cls_problem *const *problems, const uint64_t *historie
     size_t rec_words = 0;
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
-        const uint64_t tn = trace_count(p, histories[i]);
+        // a part of the run records no trace (not every traced history runs)
+        const uint64_t tn = fraction >= 1.0 ? trace_count(p, histories[i]) : 0;
         st = ensure_device(p, tn);
         if (st != CLS_OK) return st;
         if (tn > p->trace_cap) return fail(CLS_ERR_INVALID_ARG, "bound device memory too small for the trace");
@@ -733,7 +734,8 @@ cls_status run_batch_part(cls_problem *const *problems, const uint64_t *historie
     size_t off = 0;
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
-        const uint64_t tn = trace_count(p, histories[i]);
+        // a part of the run records no trace (not every traced history runs)
+        const uint64_t tn = fraction >= 1.0 ? trace_count(p, histories[i]) : 0;
         const uint64_t chunk = batch_chunk_size(histories[i], total_hist, waves_total, (uint64_t)used.max_chunk);
         fill_dev_problem(p, histories[i], seeds[i], chunk, tn, &h_probs[i]);
         h_probs[i].record = d_rec + off;
