@@ -53,6 +53,7 @@ struct Request {
     Clock::time_point t_submit, t_admit, t_done;
     uint32_t rounds = 0;
     int stream = 0;
+    bool prepared = false;   // device side done (prepare)
 };
 
 struct RoundPart {
@@ -84,6 +85,7 @@ struct cls_server {
     std::set<const cls_problem *> in_flight;   // problems with a request being submitted, pending or active
     std::map<uint64_t, Request *> all;
     uint64_t next_ticket = 1;
+    uint32_t next_stream = 0;
     size_t in_use = 0, peak = 0;
     hipStream_t streams[2] = {nullptr, nullptr};
     std::vector<RoundSlot> slots;
@@ -119,8 +121,12 @@ void finish(cls_server *s, Request *r, cls_status err)
     s->cv_done.notify_all();
 }
 
-// Admission (under the lock): reset the request's tallies on its stream.
-cls_status admit(cls_server *s, Request *r)
+// Device side of a request, done once before it is admitted: the problem's
+// workspace, its chunking, its record and the reset of its tallies on the
+// request's stream (which the other stream waits for). Called from the
+// submitting thread when it runs on the server's device, else by the worker
+// at admission; the request is not yet visible to any round.
+cls_status prepare(cls_server *s, Request *r)
 {
     cls_problem *p = r->p;
     cls_status st = ensure_device(p, 0);
@@ -145,6 +151,17 @@ cls_status admit(cls_server *s, Request *r)
     // both streams must see the reset before any round touches the tallies
     HIP_TRY(hipEventRecord(p->ev_k0, st_));
     HIP_TRY(hipStreamWaitEvent(s->streams[r->stream ^ 1], p->ev_k0, 0));
+    r->prepared = true;
+    return CLS_OK;
+}
+
+// Admission (under the lock).
+cls_status admit(cls_server *s, Request *r)
+{
+    if (!r->prepared) {
+        const cls_status st = prepare(s, r);
+        if (st != CLS_OK) return st;
+    }
     r->t_admit = Clock::now();
     r->state = RQ_ACTIVE;
     return CLS_OK;
@@ -437,14 +454,15 @@ cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, 
             delete r;
             return fail(CLS_ERR_STATE, "this problem already has a request in flight");
         }
+        r->stream = (int)(s->next_stream++ & 1u);
     }
-    // The problem's device memory is allocated here, in the caller's thread
-    // (when it runs on the server's device), so that the worker does not stall
-    // the rounds on allocations; no other request of this problem can be in
-    // the server now.
+    // The request's device side (allocation, chunking, record, tally reset)
+    // is done here, in the caller's thread, when it runs on the server's
+    // device, so that the worker does not hold the rounds back for it; no
+    // other request of this problem can be in the server now.
     int dev = -1;
     cls_status st = CLS_OK;
-    if (hipGetDevice(&dev) == hipSuccess && dev == s->device) st = ensure_device(p, 0);
+    if (hipGetDevice(&dev) == hipSuccess && dev == s->device) st = prepare(s, r);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (st == CLS_OK && s->stop) st = fail(CLS_ERR_STATE, "server is shutting down");
@@ -454,7 +472,6 @@ cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, 
             return st;
         }
         r->ticket = s->next_ticket++;
-        r->stream = (int)(r->ticket & 1);
         s->all[r->ticket] = r;
         s->pending.push_back(r);
         *ticket = r->ticket;
