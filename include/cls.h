@@ -275,9 +275,10 @@ typedef struct {
 cls_status cls_server_create(const cls_server_config *cfg, cls_server **out);
 /* Queue a run of p (not CLS_F_TRACE; one request per problem at a time; the
  * problem must not be used otherwise until the request is done). When the
- * calling thread's current device is the server's, the problem's device
- * memory is allocated by this call (CLS_ERR_OUT_OF_MEMORY, CLS_ERR_DEVICE),
- * not by the worker. */
+ * calling thread's current device is the server's, this call also prepares
+ * the request on the device (allocates the problem's memory, writes its
+ * record, resets its tallies; CLS_ERR_OUT_OF_MEMORY, CLS_ERR_DEVICE), so that
+ * the worker does not have to. */
 cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, uint64_t seed,
                              uint64_t *ticket);
 /* CLS_OK when done (read results with cls_read_tallies on the problem),
