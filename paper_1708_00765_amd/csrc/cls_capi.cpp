@@ -742,9 +742,7 @@ cls_status run_batch_part(cls_problem *const *problems, const uint64_t *historie
         off += record_words(p->nbins);
         const uint64_t items = (histories[i] + chunk - 1) / chunk;
         // a part of the run: its first chunks, cut exactly as in the whole run
-        const uint64_t take = fraction >= 1.0
-                                  ? items
-                                  : std::min(items, std::max<uint64_t>(1, (uint64_t)std::ceil(fraction * (double)items)));
+        const uint64_t take = sched::part_items(items, fraction);
         h_items[i + 1] = h_items[i] + take;
         done_hist += std::min(histories[i], take * chunk);
     }

@@ -53,6 +53,15 @@ inline uint64_t batch_chunk_size(uint64_t n, uint64_t total, uint64_t waves_tota
     return grouped_chunk_size(n, waves_total, max_chunk, (total + 32 * waves_total - 1) / (32 * waves_total));
 }
 
+// Chunks of a problem's `items` that a calibration part of a batch runs: the
+// first ceil(fraction x items), at least one, all of them for fraction >= 1.
+inline uint64_t part_items(uint64_t items, double fraction)
+{
+    if (!(fraction < 1.0)) return items;
+    const double want = std::ceil(std::max(0.0, fraction) * (double)items);
+    return std::min(items, std::max<uint64_t>(1, (uint64_t)want));
+}
+
 // Chunks of the largest size per wave that a server round holds at least: a
 // persistent launch lasts at least as long as one wave takes for its largest
 // chunk, so a round with fewer leaves most waves idle.

@@ -129,6 +129,19 @@ int main()
         }
         ++cases;
     }
+    // calibration parts of a batch
+    for (int t = 0; t < 100000; ++t) {
+        const uint64_t items = log_uniform(1, 1e7);
+        std::uniform_real_distribution<double> uf(-0.5, 1.5);
+        const double f = uf(rng);
+        const uint64_t k = part_items(items, f);
+        CHECK(k >= 1 && k <= items, "items %llu f %g -> %llu", (unsigned long long)items, f, (unsigned long long)k);
+        if (f >= 1.0) CHECK(k == items, "whole run cut: %llu of %llu", (unsigned long long)k, (unsigned long long)items);
+        if (f > 0.0 && f < 1.0)
+            CHECK((double)k >= f * (double)items && (double)(k - 1) < f * (double)items,
+                  "items %llu f %g -> %llu", (unsigned long long)items, f, (unsigned long long)k);
+        ++cases;
+    }
     printf("%s %ld cases, %d failures\n", failures ? "FAILED" : "OK", cases, failures);
     return failures ? 1 : 0;
 }
