@@ -143,8 +143,13 @@ static void release_device(cls_problem *p)
 cls_status ensure_device(cls_problem *p, uint64_t trace_n)
 {
     DeviceInfo di;
-    cls_status st = device_info(&di);
+    const cls_status st = device_info(&di);
     if (st != CLS_OK) return st;
+    return ensure_device(p, trace_n, di);
+}
+
+cls_status ensure_device(cls_problem *p, uint64_t trace_n, const DeviceInfo &di)
+{
     if (p->device >= 0 && p->device != di.id)
         return fail(CLS_ERR_STATE, "problem was first run on another device");
     p->device = di.id;
@@ -496,7 +501,7 @@ cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed)
     if (st != CLS_OK) return st;
     if (trace_n > p->trace_cap) return fail(CLS_ERR_INVALID_ARG, "bound device memory too small for the trace");
     // the previous run must be done before its host mirrors are rewritten
-    if (p->has_run) HIP_TRY(hipEventSynchronize(p->ev_done));
+    if (p->has_run && !p->done_synced) HIP_TRY(hipEventSynchronize(p->ev_done));
     DeviceInfo di;
     st = device_info(&di);
     if (st != CLS_OK) return st;
@@ -536,6 +541,7 @@ cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed)
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(p->ev_done, s));
     p->has_run = true;
+    p->done_synced = false;
     p->timed_by_events = true;
     p->histories = histories;
     p->seed = seed;
@@ -558,6 +564,7 @@ cls_status cls_synchronize(cls_problem *p)
     if (!p) return fail(CLS_ERR_INVALID_ARG, "problem is NULL");
     if (!p->has_run) return fail(CLS_ERR_STATE, "no run");
     HIP_TRY(hipEventSynchronize(p->ev_done));
+    p->done_synced = true;
     return CLS_OK;
 }
 
@@ -577,9 +584,11 @@ cls_status cls_read_tallies(const cls_problem *p, cls_tallies *out, double *flux
     if (!p || !out) return fail(CLS_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_run) return fail(CLS_ERR_STATE, "no completed run");
     if ((flux || flux_sigma) && nbins != p->nbins) return fail(CLS_ERR_INVALID_ARG, "nbins does not match the problem");
-    hipError_t e = hipEventQuery(p->ev_done);
-    if (e == hipErrorNotReady) return fail(CLS_ERR_NOT_READY, "the last run has not completed");
-    if (e != hipSuccess) return hip_fail(e, "hipEventQuery");
+    if (!p->done_synced) {
+        const hipError_t e = hipEventQuery(p->ev_done);
+        if (e == hipErrorNotReady) return fail(CLS_ERR_NOT_READY, "the last run has not completed");
+        if (e != hipSuccess) return hip_fail(e, "hipEventQuery");
+    }
     const uint64_t *C = p->h_record;
     const double *Rz = (const double *)(p->h_record + C_COUNT);
     std::memset(out, 0, sizeof *out);
@@ -687,22 +696,22 @@ cls_status run_batch_part(cls_problem *const *problems, const uint64_t *historie
     cls_status st = check_problem_set(problems, n, histories, &total_hist, "batch");
     if (st != CLS_OK) return st;
     std::lock_guard<std::mutex> lk(g_batch_mu);
+    DeviceInfo di;
+    st = device_info(&di);
+    if (st != CLS_OK) return st;
     int max_bins = 1;
     size_t rec_words = 0;
     for (int i = 0; i < n; ++i) {
         cls_problem *p = problems[i];
         // a part of the run records no trace (not every traced history runs)
         const uint64_t tn = fraction >= 1.0 ? trace_count(p, histories[i]) : 0;
-        st = ensure_device(p, tn);
+        st = ensure_device(p, tn, di);
         if (st != CLS_OK) return st;
         if (tn > p->trace_cap) return fail(CLS_ERR_INVALID_ARG, "bound device memory too small for the trace");
-        if (p->has_run) HIP_TRY(hipEventSynchronize(p->ev_done));
+        if (p->has_run && !p->done_synced) HIP_TRY(hipEventSynchronize(p->ev_done));
         max_bins = std::max(max_bins, p->nbins);
         rec_words += record_words(p->nbins);
     }
-    DeviceInfo di;
-    st = device_info(&di);
-    if (st != CLS_OK) return st;
     int grid, block, stride;
     size_t lds;
     LaunchShape used;
@@ -763,9 +772,8 @@ cls_status run_batch_part(cls_problem *const *problems, const uint64_t *historie
     HIP_TRY(hipEventRecord(bs->k1, s));
     HIP_TRY(launch_finalize(d_probs, n, s));
     HIP_TRY(hipMemcpyAsync(h_rec, d_rec, rec_words * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    // completion events of every problem precede the batch event on the stream,
-    // so they have all fired once the batch event has
-    for (int i = 0; i < n; ++i) HIP_TRY(hipEventRecord(problems[i]->ev_done, s));
+    // the call is synchronous: once the batch event has fired every problem's
+    // results are complete (done_synced below), so no per-problem event is recorded
     HIP_TRY(hipEventRecord(bs->done, s));
     HIP_TRY(hipEventSynchronize(bs->done));
     float ms = 0.0f;
@@ -777,6 +785,7 @@ cls_status run_batch_part(cls_problem *const *problems, const uint64_t *historie
         std::memcpy(p->h_record, h_rec + off, record_words(p->nbins) * sizeof(uint64_t));
         off += record_words(p->nbins);
         p->has_run = true;
+        p->done_synced = true;
         p->timed_by_events = false;
         p->track_ms = ms;
         p->histories = histories[i];

@@ -133,7 +133,7 @@ cls_status cls_batch_run(cls_batch *b, const uint64_t *histories, const uint64_t
     const cls_status chk = check_problem_set(b->probs.data(), n, histories, &total, "batch");
     if (chk != CLS_OK) return chk;
     for (cls_problem *p : b->probs)
-        if (p->has_run) HIP_TRY(hipEventSynchronize(p->ev_done));
+        if (p->has_run && !p->done_synced) HIP_TRY(hipEventSynchronize(p->ev_done));
     DevProblem *h_probs = (DevProblem *)b->host;
     uint64_t *h_items = (uint64_t *)(b->host + b->probs_bytes);
     uint64_t *h_rec = (uint64_t *)(b->host + b->probs_bytes + b->items_bytes);
@@ -177,7 +177,6 @@ cls_status cls_batch_run(cls_batch *b, const uint64_t *histories, const uint64_t
     HIP_TRY(hipEventRecord(b->t0, b->stream));
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     HIP_TRY(hipEventRecord(b->t1, b->stream));
-    for (cls_problem *p : b->probs) HIP_TRY(hipEventRecord(p->ev_done, b->stream));
     HIP_TRY(hipEventRecord(b->done, b->stream));
     HIP_TRY(hipEventSynchronize(b->done));
     float ms = 0.0f;
@@ -189,6 +188,7 @@ cls_status cls_batch_run(cls_batch *b, const uint64_t *histories, const uint64_t
         std::memcpy(p->h_record, h_rec + off, record_words(p->nbins) * sizeof(uint64_t));
         off += record_words(p->nbins);
         p->has_run = true;
+        p->done_synced = true;
         p->timed_by_events = false;
         p->track_ms = ms;
         p->histories = histories[i];

@@ -46,6 +46,7 @@ struct cls_problem {
     // run state
     hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr, ev_done = nullptr;
     bool has_run = false;
+    bool done_synced = false;       // the last run is known complete (a synchronous path waited for it)
     bool timed_by_events = false;   // track_ms comes from ev_k0/ev_k1
     float track_ms = 0.0f;
     uint64_t histories = 0, seed = 0, trace_n = 0;
@@ -77,6 +78,8 @@ LaunchShape current_shape();
 size_t align256(size_t v);
 size_t workspace_bytes(int nbins, uint64_t trace_n);
 cls_status ensure_device(cls_problem *p, uint64_t trace_n);
+// The same with the current device's info already at hand (loops over problems).
+cls_status ensure_device(cls_problem *p, uint64_t trace_n, const DeviceInfo &di);
 uint64_t trace_count(const cls_problem *p, uint64_t histories);
 using sched::batch_chunk_size;
 using sched::chunk_size;

@@ -143,7 +143,7 @@ cls_status prepare(cls_server *s, Request *r)
     const uint64_t round_share = std::max<uint64_t>(1, s->cfg.round_histories / waves_total);
     r->chunk = grouped_chunk_size(r->histories, waves_total, (uint64_t)sh.max_chunk, round_share);
     r->n_chunks = (r->histories + r->chunk - 1) / r->chunk;
-    if (p->has_run) HIP_TRY(hipEventSynchronize(p->ev_done));
+    if (p->has_run && !p->done_synced) HIP_TRY(hipEventSynchronize(p->ev_done));
     fill_dev_problem(p, r->histories, r->seed, r->chunk, 0, p->h_prob);
     hipStream_t st_ = s->streams[r->stream];
     HIP_TRY(hipMemcpyAsync(p->d_prob, p->h_prob, sizeof(DevProblem), hipMemcpyHostToDevice, st_));
@@ -303,6 +303,7 @@ cls_status start_finalize(cls_server *s, Request *r)
     HIP_TRY(hipMemcpyAsync(p->h_record, p->d_record, record_words(p->nbins) * sizeof(uint64_t),
                            hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(p->ev_done, st));
+    p->done_synced = false;
     r->state = RQ_FINALIZING;
     return CLS_OK;
 }
@@ -352,6 +353,7 @@ void worker_main(cls_server *s)
                     if (q == hipSuccess) {
                         cls_problem *p = r->p;
                         p->has_run = true;
+                        p->done_synced = true;     // ev_done was seen complete above
                         p->timed_by_events = false;
                         p->track_ms = 0.0f;
                         p->histories = r->histories;
