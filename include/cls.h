@@ -247,7 +247,7 @@ cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories,
  * A worker thread admits requests, runs rounds of one persistent launch over
  * the next chunks of every admitted request of one kernel variant, and copies
  * each request's results back when its last chunk is done. A round holds at
- * least round_histories and at least three of its largest chunks per resident
+ * least round_histories and at least six of its largest chunks per resident
  * wave (a round lasts at least as long as one wave takes for its largest
  * chunk), shared equally between its requests: one with less left finishes in
  * that round, the others get equal shares of the rest (at least one chunk).

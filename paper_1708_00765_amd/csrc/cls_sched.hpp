@@ -64,8 +64,9 @@ inline uint64_t part_items(uint64_t items, double fraction)
 
 // Chunks of the largest size per wave that a server round holds at least: a
 // persistent launch lasts at least as long as one wave takes for its largest
-// chunk, so a round with fewer leaves most waves idle.
-constexpr double kRoundChunksPerWave = 3.0;
+// chunk, so a round with fewer leaves most waves idle (measured on the served
+// mix at saturation: 3 -> 6 gained 3% at equal latency).
+constexpr double kRoundChunksPerWave = 6.0;
 
 // Histories a server round aims at: at least round_histories and at least
 // kRoundChunksPerWave of its largest chunks per wave.

@@ -94,7 +94,7 @@ int main()
         }
         const uint64_t waves = log_uniform(64, 9000);
         const double budget = round_budget(3e7, waves, largest);
-        CHECK(budget >= 3e7 && budget >= 3.0 * (double)waves * (double)largest, "budget %g", budget);
+        CHECK(budget >= 3e7 && budget >= kRoundChunksPerWave * (double)waves * (double)largest, "budget %g", budget);
         const std::vector<uint64_t> take = water_fill(claims, budget);
         // the level lies in [h_i, h_i + chunk_i) for every request cut to more than one chunk
         double got = 0.0, level_lo = 0.0, level_hi = 1e300;

@@ -272,12 +272,12 @@ def test_fine_mesh_batch_with_tiny_problems_equals_single_runs(cls):
 
 def test_served_rounds_split_big_requests_and_keep_results(cls):
     """Two big fine-mesh requests and a few tiny ones submitted at once to a
-    default server: a round holds at most ~3 of the largest chunks per wave
-    (~2.4e8 to 3.9e8 histories for these meshes), shared equally between the
-    requests, so each big request (5e8 histories) runs over several rounds
+    default server: a round holds about 6 of the largest chunks per wave
+    (~4.8e8 to 7.8e8 histories for these meshes), shared equally between the
+    requests, so each big request (1.2e9 histories) runs over several rounds
     while a tiny one finishes in the round it joins; each result equals its
     lone run (counts exactly, flux to summation order)."""
-    specs = _fine_mesh_mix(500_000_000, 2, 6, seed=2)
+    specs = _fine_mesh_mix(1_200_000_000, 2, 6, seed=2)
     _print("served mix:", [(s.histories, s.nbins) for s in specs])
     probs = [gpu_problem(s, fp32=True) for s in specs]
     srv = cls.cls_server_create()
