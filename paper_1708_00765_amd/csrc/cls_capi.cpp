@@ -14,7 +14,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -265,6 +267,30 @@ Variant variant_of(const cls_problem *p)
     return v;
 }
 
+// Occupancy of a tracking-kernel variant for a workgroup size and LDS size on
+// the current device, cached: the answer never changes within a process, and
+// the query is a runtime call that every launch-shape choice makes up to
+// eight times.
+static hipError_t occupancy_cached(const Variant &v, int device, int block, size_t lds, int *bpc)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, bool, bool, int, size_t>, int> cache;
+    const auto key = std::make_tuple(device, v.geom, v.est, v.src, v.fp32, v.trace, block, lds);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto it = cache.find(key);
+        if (it != cache.end()) {
+            *bpc = it->second;
+            return hipSuccess;
+        }
+    }
+    const hipError_t e = track_occupancy(v, block, lds, bpc);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = *bpc;
+    return hipSuccess;
+}
+
 // Launch shape. Each wave needs one or two LDS tally buffers (two let a
 // wave start its next chunk while the last histories of the previous one
 // finish; one halves the LDS, at the cost of waiting for those histories,
@@ -294,7 +320,7 @@ cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *
             if (pw * (size_t)c > limit) continue;
             int bpc = s.blocks_per_cu;
             if (bpc <= 0) {
-                const hipError_t e = track_occupancy(v, c * 64, pw * (size_t)c, &bpc);
+                const hipError_t e = occupancy_cached(v, di.id, c * 64, pw * (size_t)c, &bpc);
                 if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
             }
             if (slots == 1) {
@@ -312,7 +338,7 @@ cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *
         while (best_waves > 1 && per_wave * (size_t)best_waves > limit) --best_waves;
         best_bpc = s.blocks_per_cu;
         if (best_bpc <= 0) {
-            const hipError_t e = track_occupancy(v, best_waves * 64, per_wave * (size_t)best_waves, &best_bpc);
+            const hipError_t e = occupancy_cached(v, di.id, best_waves * 64, per_wave * (size_t)best_waves, &best_bpc);
             if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
         }
     }
