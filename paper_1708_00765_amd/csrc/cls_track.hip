@@ -21,11 +21,16 @@
 //    flight: histories of the chunk being started go to one, stragglers of the
 //    previous chunk finish in the other, and a chunk's buffer is flushed to
 //    HBM with FP64 atomics once its last history ends, so a chunk is exactly
-//    one batch of the batch-means flux error with no tail stall;
-//  * track-length flux goes to the LDS buffer in difference form (at most four
-//    LDS FP64 atomics per flight whatever the number of bins crossed); the
-//    flush prefix-scans it across the wave;
-//  * integer tallies are wave-level ballot counts kept in scalar registers.
+//    one batch of the batch-means flux error with no tail stall (with fine
+//    meshes a launch may give each wave one buffer, which then waits for its
+//    chunk's last history before it claims the next);
+//  * track-length flux goes to the LDS buffer in difference form (four LDS
+//    FP64 atomics per flight whatever the number of bins crossed); the flush
+//    prefix-scans it across the wave;
+//  * per-history scores and event counts are summed in each lane's registers
+//    over its histories in a slot and reach the slot's LDS counters only when
+//    the lane changes slot or the slot is flushed; flights and collisions are
+//    derived at the flush.
 #include <type_traits>
 
 #include "cls_internal.hpp"
