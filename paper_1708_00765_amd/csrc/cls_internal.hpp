@@ -73,11 +73,11 @@ struct TrackArgs {
     int nprobs;
     int lds_stride;              // doubles per tally buffer (>= max nbins + 1, even)
     int refill_min;              // idle lanes a wave waits for before handing out histories
-    int slots;                   // LDS tally buffers per wave: 2, or 1 for large meshes
+    int slots;                   // LDS tally buffers per wave: 2, or 1 (fine meshes, large chunks)
 };
 
-// LDS per wave beyond its two tally buffers: score sums of the two slots
-// (4 doubles) and kSlotCounters 32-bit counters per slot.
+// LDS per wave beyond its one or two tally buffers: score sums of two slots
+// (4 doubles) and kSlotCounters 32-bit counters per slot (12 doubles).
 constexpr int kSlotCounters = 12;
 // ... then the per-material flight parameters of the problem each slot holds:
 // 2 slots x 2 materials x 4 values, room for FP64 values.
