@@ -24,6 +24,7 @@ enum Event : int {
 enum Counter : int {
     C_HISTORIES = 0, C_TRANSMITTED, C_REFLECTED, C_ABSORBED, C_CAPPED,
     C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_INTERFACES, C_LATERAL, C_BATCHES,
+    C_DONE_CHUNKS,              // chunks flushed (in-kernel finalize of served requests)
     C_COUNT = 16
 };
 
@@ -63,6 +64,11 @@ struct alignas(16) DevProblem {
     uint64_t *record;           // finalize output, record_words(K) words
     uint64_t *trace_hash;
     uint32_t *trace_len;
+    // Served requests: the request's total chunk count, and the device address
+    // of its pinned host record. When non-zero, the wave that flushes the last
+    // chunk writes the finalized record there (no finalize kernel or copy).
+    uint64_t final_chunks;
+    uint64_t *host_record;
 };
 
 // Everything one tracking launch needs.
@@ -74,6 +80,7 @@ struct TrackArgs {
     int lds_stride;              // doubles per tally buffer (>= max nbins + 1, even)
     int refill_min;              // idle lanes a wave waits for before handing out histories
     int slots;                   // LDS tally buffers per wave: 2, or 1 (fine meshes, large chunks)
+    unsigned long long *exit_count = nullptr;   // served rounds: waves that have left (zeroed before)
 };
 
 // LDS per wave beyond its one or two tally buffers: score sums of two slots

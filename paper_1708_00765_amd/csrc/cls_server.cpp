@@ -54,6 +54,7 @@ struct Request {
     uint32_t rounds = 0;
     int stream = 0;
     bool prepared = false;   // device side done (prepare)
+    uint64_t *host_record = nullptr;   // device address of the problem's pinned record (0: finalize kernel)
 };
 
 struct RoundPart {
@@ -151,6 +152,11 @@ cls_status prepare(cls_server *s, Request *r)
     // both streams must see the reset before any round touches the tallies
     HIP_TRY(hipEventRecord(p->ev_k0, st_));
     HIP_TRY(hipStreamWaitEvent(s->streams[r->stream ^ 1], p->ev_k0, 0));
+    // the round that completes the request writes its record straight into the
+    // pinned host record when the device can address it; else a finalize
+    // kernel and a copy follow the request's last round
+    void *dptr = nullptr;
+    r->host_record = hipHostGetDevicePointer(&dptr, p->h_record, 0) == hipSuccess ? (uint64_t *)dptr : nullptr;
     r->prepared = true;
     return CLS_OK;
 }
@@ -244,7 +250,8 @@ bool launch_round(cls_server *s, RoundSlot &sl, cls_status *err)
                      [](const RoundPart &a, const RoundPart &b) { return a.r->chunk > b.r->chunk; });
     const int n = (int)sl.parts.size();
     const size_t probs_bytes = align256((size_t)n * sizeof(DevProblem));
-    const size_t items_bytes = align256(((size_t)n + 2) * sizeof(uint64_t));
+    // item prefix sums, the queue head and the count of waves that have left
+    const size_t items_bytes = align256(((size_t)n + 3) * sizeof(uint64_t));
     if (*err == CLS_OK) {
         const double share = small_share_of(sl.parts);
         *err = shape_for(v, max_bins, s->di, &grid, &block, &lds, &stride, &used,
@@ -264,9 +271,14 @@ bool launch_round(cls_server *s, RoundSlot &sl, cls_status *err)
         Request *r = sl.parts[i].r;
         fill_dev_problem(r->p, r->histories, r->seed, r->chunk, 0, &h_probs[i]);
         h_probs[i].chunk_base = r->next_chunk;
+        if (r->host_record) {
+            h_probs[i].final_chunks = r->n_chunks;
+            h_probs[i].host_record = r->host_record;
+        }
         h_items[i + 1] = h_items[i] + sl.parts[i].chunks;
     }
     h_items[n + 1] = 0;
+    h_items[n + 2] = 0;
     hipStream_t st = s->streams[sl.stream];
     TrackArgs a;
     a.probs = (const DevProblem *)sl.dev;
@@ -276,6 +288,7 @@ bool launch_round(cls_server *s, RoundSlot &sl, cls_status *err)
     a.lds_stride = stride;
     a.refill_min = used.refill_min;
     a.slots = used.slots;
+    a.exit_count = (unsigned long long *)(sl.dev + probs_bytes) + n + 2;
     hipError_t e = hipMemcpyAsync(sl.dev, sl.host, probs_bytes + items_bytes, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_track(v, a, grid, block, lds, st);
     if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
@@ -294,7 +307,22 @@ bool launch_round(cls_server *s, RoundSlot &sl, cls_status *err)
     return true;
 }
 
-// A request whose chunks all completed: finalize and copy its results back.
+// A request whose results are in its problem's host record.
+void complete(cls_server *s, Request *r)
+{
+    cls_problem *p = r->p;
+    p->has_run = true;
+    p->done_synced = true;
+    p->timed_by_events = false;
+    p->track_ms = 0.0f;
+    p->histories = r->histories;
+    p->seed = r->seed;
+    p->trace_n = 0;
+    finish(s, r, p->h_record[C_CAPPED] ? CLS_ERR_EVENT_CAP : CLS_OK);
+}
+
+// A request whose chunks all completed (no device-addressable host record):
+// finalize and copy its results back.
 cls_status start_finalize(cls_server *s, Request *r)
 {
     cls_problem *p = r->p;
@@ -338,8 +366,14 @@ void worker_main(cls_server *s)
                 }
                 r->done_chunks += part.chunks;
                 if (r->state == RQ_ACTIVE && r->done_chunks == r->n_chunks) {
-                    const cls_status st = start_finalize(s, r);
-                    if (st != CLS_OK) finish(s, r, st);
+                    if (r->host_record) {
+                        // every round with its chunks has completed, and the last
+                        // of them wrote the record into the pinned host record
+                        complete(s, r);
+                    } else {
+                        const cls_status st = start_finalize(s, r);
+                        if (st != CLS_OK) finish(s, r, st);
+                    }
                 }
             }
             sl.parts.clear();
@@ -351,15 +385,7 @@ void worker_main(cls_server *s)
                 const hipError_t q = hipEventQuery(r->p->ev_done);
                 if (q != hipErrorNotReady) {
                     if (q == hipSuccess) {
-                        cls_problem *p = r->p;
-                        p->has_run = true;
-                        p->done_synced = true;     // ev_done was seen complete above
-                        p->timed_by_events = false;
-                        p->track_ms = 0.0f;
-                        p->histories = r->histories;
-                        p->seed = r->seed;
-                        p->trace_n = 0;
-                        finish(s, r, p->h_record[C_CAPPED] ? CLS_ERR_EVENT_CAP : CLS_OK);
+                        complete(s, r);            // ev_done was seen complete above
                     } else {
                         finish(s, r, hip_fail(q, "result copy"));
                     }

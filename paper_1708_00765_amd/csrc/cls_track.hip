@@ -478,6 +478,74 @@ struct SlotState {
     int32_t pid, open;
 };
 
+// ---------------------------------------------------------------------------
+// finalize: means and one-sigma errors per source history
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mean_sigma(double sum, double sq, double n, double *mean, double *sig)
+{
+    const double mu = n > 0.0 ? sum / n : 0.0;
+    double var = n > 1.0 ? (sq / n - mu * mu) * n / (n - 1.0) : 0.0;
+    var = var > 0.0 ? var : 0.0;
+    *mean = mu;
+    *sig = n > 1.0 ? sqrt(var / n) : 0.0;
+}
+
+// Loads of the problem's tallies: plain in the finalize kernel (a later kernel
+// than the tracking one), from L2 (device-scope atomic loads) when a tracking
+// wave finalizes after the other waves' flush atomics.
+template <bool L2>
+__device__ __forceinline__ uint64_t tally_u(const uint64_t *p)
+{
+    if (L2) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+template <bool L2>
+__device__ __forceinline__ double tally_d(const double *p)
+{
+    if (L2) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+
+// The result record of a problem from its tallies, written by threads t of
+// nt: the counters, T, R, A and the total flux with their binomial or
+// per-history errors, and the per-bin flux with its batch-means error.
+template <bool L2, typename PR>
+__device__ __forceinline__ void record_into(PR &P, uint64_t *rec, int t, int nt)
+{
+    const int K = P.nbins;
+    const uint64_t *C = P.counters;
+    const double n = (double)tally_u<L2>(C + C_HISTORIES);
+    const double B = (double)tally_u<L2>(C + C_BATCHES);
+    double *out = (double *)(rec + C_COUNT);
+    for (int i = t; i < C_COUNT; i += nt) rec[i] = tally_u<L2>(C + i);
+    if (t == 0) {
+        double mu, sg;
+        const double nt_ = (double)tally_u<L2>(C + C_TRANSMITTED);
+        const double nr_ = (double)tally_u<L2>(C + C_REFLECTED);
+        const double na_ = (double)tally_u<L2>(C + C_ABSORBED);
+        mean_sigma(nt_, nt_, n, &mu, &sg);
+        out[R_T] = mu; out[R_SIGMA_T] = sg;
+        mean_sigma(nr_, nr_, n, &mu, &sg);
+        out[R_R] = mu; out[R_SIGMA_R] = sg;
+        mean_sigma(na_, na_, n, &mu, &sg);
+        out[R_A] = mu; out[R_SIGMA_A] = sg;
+        mean_sigma(tally_d<L2>(P.sums), tally_d<L2>(P.sums + 1), n, &mu, &sg);
+        out[R_TOTAL] = mu; out[R_SIGMA_TOTAL] = sg;
+    }
+    // batch means: chunk b holds n_b histories with bin score s_b; with
+    // S = sum s_b and Q = sum s_b^2 / n_b the per-history variance is
+    // (Q - S^2/N) / (B - 1) and the error of the mean its square root over N.
+    for (int k = t; k < K; k += nt) {
+        const double S = tally_d<L2>(P.sums + 2 + k);
+        const double Q = tally_d<L2>(P.sums + 2 + K + k);
+        const double mu = n > 0.0 ? S / n : 0.0;
+        double var = B > 1.0 ? (Q - S * mu) / (B - 1.0) : 0.0;
+        var = var > 0.0 ? var : 0.0;
+        out[R_HEADER + k] = mu / P.dx;
+        out[R_HEADER + K + k] = (n > 0.0 && B > 1.0) ? sqrt(var / n) / P.dx : 0.0;
+    }
+}
+
 // Move a lane's sums to the LDS counters of its slot (a lane that finished no
 // history there holds none) and clear them.
 template <typename R>
@@ -553,6 +621,13 @@ __device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, dou
         atomicAdd(P.sums + 1, st2);
     }
     S.open = 0;
+    if (P.final_chunks != 0) {
+        // A served request: its flushed chunks are counted (after this wave's
+        // flush atomics have completed); the last wave of the launch writes
+        // the records of the requests whose chunks are all done.
+        __threadfence();
+        if (lane == 0) atomicAdd(Cg + C_DONE_CHUNKS, 1ull);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -730,6 +805,31 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             }
         }
     }
+
+    // ---------------- served requests: records of the finished ones ----------
+    // The last wave of the launch to leave writes the record of every request
+    // of the launch whose chunks are all flushed (in this launch or one that
+    // ran beside it) into its pinned host record, so that no finalize kernel
+    // or copy has to wait for compute units behind another launch.
+    if (A.exit_count) {
+        __threadfence();
+        unsigned long long left = 0;
+        if (lane == 0) left = atomicAdd(A.exit_count, 1ull);
+        left = ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(left >> 32), 0) << 32) |
+               (unsigned long long)__builtin_amdgcn_readlane((uint32_t)left, 0);
+        const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x / 64u);
+        if (left + 1 == waves) {
+            __threadfence();
+            for (int i = 0; i < A.nprobs; ++i) {
+                ConstProblem &P = ((ConstProblem *)A.probs)[i];
+                if (P.final_chunks == 0) continue;
+                const uint64_t done = __hip_atomic_load((const uint64_t *)P.counters + C_DONE_CHUNKS, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                if (done == P.final_chunks) record_into<true>(P, P.host_record, lane, 64);
+            }
+            __threadfence_system();
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -745,50 +845,12 @@ __global__ void reset_kernel(const DevProblem *probs, uint64_t *queue_head)
 }
 
 // ---------------------------------------------------------------------------
-// finalize: means and one-sigma errors per source history
+// finalize kernel: one workgroup per problem (record_into above)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void mean_sigma(double sum, double sq, double n, double *mean, double *sig)
-{
-    const double mu = n > 0.0 ? sum / n : 0.0;
-    double var = n > 1.0 ? (sq / n - mu * mu) * n / (n - 1.0) : 0.0;
-    var = var > 0.0 ? var : 0.0;
-    *mean = mu;
-    *sig = n > 1.0 ? sqrt(var / n) : 0.0;
-}
-
 __global__ void finalize_kernel(const DevProblem *probs)
 {
     const DevProblem &P = probs[blockIdx.x];
-    const int K = P.nbins;
-    const uint64_t *C = P.counters;
-    const double n = (double)C[C_HISTORIES];
-    const double B = (double)C[C_BATCHES];
-    uint64_t *rec = P.record;
-    double *out = (double *)(rec + C_COUNT);
-    for (int i = threadIdx.x; i < C_COUNT; i += blockDim.x) rec[i] = C[i];
-    if (threadIdx.x == 0) {
-        double mu, sg;
-        mean_sigma((double)C[C_TRANSMITTED], (double)C[C_TRANSMITTED], n, &mu, &sg);
-        out[R_T] = mu; out[R_SIGMA_T] = sg;
-        mean_sigma((double)C[C_REFLECTED], (double)C[C_REFLECTED], n, &mu, &sg);
-        out[R_R] = mu; out[R_SIGMA_R] = sg;
-        mean_sigma((double)C[C_ABSORBED], (double)C[C_ABSORBED], n, &mu, &sg);
-        out[R_A] = mu; out[R_SIGMA_A] = sg;
-        mean_sigma(P.sums[0], P.sums[1], n, &mu, &sg);
-        out[R_TOTAL] = mu; out[R_SIGMA_TOTAL] = sg;
-    }
-    // batch means: chunk b holds n_b histories with bin score s_b; with
-    // S = sum s_b and Q = sum s_b^2 / n_b the per-history variance is
-    // (Q - S^2/N) / (B - 1) and the error of the mean its square root over N.
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        const double S = P.sums[2 + k];
-        const double Q = P.sums[2 + K + k];
-        const double mu = n > 0.0 ? S / n : 0.0;
-        double var = B > 1.0 ? (Q - S * mu) / (B - 1.0) : 0.0;
-        var = var > 0.0 ? var : 0.0;
-        out[R_HEADER + k] = mu / P.dx;
-        out[R_HEADER + K + k] = (n > 0.0 && B > 1.0) ? sqrt(var / n) / P.dx : 0.0;
-    }
+    record_into<false>(P, P.record, (int)threadIdx.x, (int)blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
