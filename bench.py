@@ -282,6 +282,13 @@ def run_quenched_leg(cls, torch, stream, perf_model, histories):
                          "frac": achieved / peak, "algorithmic_slots": slots}}
 
 
+def _span(values):
+    """One value, or the range of a mix (as "1e4 to 1e7")."""
+    v = list(values)
+    lo, hi = min(v), max(v)
+    return f"{lo:g}" if lo == hi else f"{lo:g} to {hi:g}"
+
+
 def run_ext2d_comparison(cls, torch, stream, steps):
     """The 256 uneven ext2d sets (1e4..1e7 histories, 100..1000 bins): one batched
     FP32 persistent launch per pass vs one plain FP64 launch per set."""
@@ -649,8 +656,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {len(specs)} sets x {specs[0].histories:g} histories, "
-                               f"d={specs[0].d} ({geom}), L={specs[0].L:g}, {specs[0].nbins} x-bins, "
+        "config": {"workload": f"{args.workload}: {len(specs)} sets x {_span(s.histories for s in specs)} histories, "
+                               f"d={specs[0].d} ({geom}), L={specs[0].L:g}, {_span(s.nbins for s in specs)} x-bins, "
                                f"{'collision' if specs[0].collision else 'track-length'} flux, "
                                "FP32 tracking with FP64 tallies, one batched persistent launch per step",
                    "sets": len(specs), "histories_per_step": total_hist},
