@@ -73,8 +73,12 @@ enum {
                                        is the track-length estimator (Sec. 3.3)       */
     CLS_F_FP32 = 1u << 2,           /* FP32 flight arithmetic, FP64 x-position and
                                        tallies; default is FP64 throughout            */
-    CLS_F_TRACE = 1u << 3           /* FP64 only: record an event hash and the flight
-                                       count of the first histories (cls_read_trace)  */
+    CLS_F_TRACE = 1u << 3,          /* record an event hash and the flight count of
+                                       the first histories (cls_read_trace)            */
+    CLS_F_TRACE_NO_BINS = 1u << 4   /* with CLS_F_TRACE: hash the events and materials
+                                       only, not the bin of each event (compares event
+                                       sequences across tracking precisions, whose
+                                       positions differ by rounding)                  */
 };
 
 /* Largest flux mesh. */
@@ -93,7 +97,7 @@ typedef struct cls_problem cls_problem;
  *   boundaries CLS_BC_DEFAULT or the equal explicit mask (see above).
  *   nbins      flux mesh size in [1, CLS_MAX_BINS]; bin k = [k L/K, (k+1) L/K),
  *              x = L belongs to the last bin.
- *   flags      CLS_F_* bits; CLS_F_TRACE requires FP64 (not CLS_F_FP32).
+ *   flags      CLS_F_* bits; CLS_F_TRACE_NO_BINS requires CLS_F_TRACE.
  *   out        receives the handle (library-owned; free with cls_destroy_problem).
  * Errors: CLS_ERR_INVALID_ARG for any value outside these ranges or a NaN/Inf;
  * CLS_ERR_OUT_OF_MEMORY. */
@@ -166,7 +170,12 @@ cls_status cls_read_tallies(const cls_problem *p, cls_tallies *out, double *flux
 
 /* Copy the trace of histories 0 .. n-1 of the last run of a CLS_F_TRACE problem:
  * hash[i] = FNV-1a-64 over the 4-byte tuples (event code, material, bin low
- * byte, bin high byte) of history i, flights[i] = its number of flights.
+ * byte, bin high byte) of history i -- with CLS_F_TRACE_NO_BINS both bin bytes
+ * are 0 -- and flights[i] = its number of flights. Event codes: 0 source,
+ * 1 interface crossing, 2 scattering, 3 absorption, 4 leak at x = 0, 5 leak at
+ * x = L, 6/7 mirror at y = 0 / L, 8/9 mirror at z = 0 / L, 10 flight cap. FP32
+ * and FP64 tracking draw the same uniforms, so a history's hash differs between
+ * them only where FP32 rounding changed one of its events.
  * n must not exceed min(histories, trace_histories). */
 cls_status cls_read_trace(const cls_problem *p, uint64_t *hash, uint32_t *flights, uint64_t n);
 

@@ -42,6 +42,7 @@ CLS_F_D1_SLAB = 1 << 0
 CLS_F_COLLISION_FLUX = 1 << 1
 CLS_F_FP32 = 1 << 2
 CLS_F_TRACE = 1 << 3
+CLS_F_TRACE_NO_BINS = 1 << 4
 
 CLS_MAX_BINS = 2048
 

@@ -182,6 +182,17 @@ cls_status ensure_device(cls_problem *p, uint64_t trace_n, const DeviceInfo &di)
     return CLS_OK;
 }
 
+// Integer form of the test U < q for the uniforms U = (k + 1/2) 2^-23 of the
+// random-number stream: U < q exactly when k < ceil(q 2^23 - 1/2) (both sides
+// are exact in FP64), i.e. when the bit pattern 0x3F800000 | k that the
+// kernels hold is below 0x3F800000 + ceil(q 2^23 - 1/2).
+uint32_t unit_threshold(double q)
+{
+    double t = std::ceil(std::ldexp(q, 23) - 0.5);
+    t = std::min(std::max(t, 0.0), 8388608.0);
+    return 0x3F800000u + (uint32_t)t;
+}
+
 void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,
                              uint64_t trace_n, DevProblem *out)
 {
@@ -205,7 +216,10 @@ void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, u
         out->lamf[i] = (float)p->lam[i];
         out->dsigf[i] = (float)(-0.69314718055994530942 / p->sigma[i]);
         out->dlamf[i] = (float)(-0.69314718055994530942 * p->lam[i]);
+        out->cthr[i] = unit_threshold(p->c[i]);
     }
+    out->p0thr = unit_threshold(out->p0);
+    out->trace_bins = (p->flags & CLS_F_TRACE_NO_BINS) ? 0 : 1;
     out->seed = seed;
     out->histories = histories;
     out->chunk = chunk;
@@ -399,11 +413,11 @@ cls_status cls_create_problem(int d, double L, const double sigma_t[2], const do
     if (source != CLS_SRC_FACE_X0 && source != CLS_SRC_VOLUME)
         return fail(CLS_ERR_INVALID_ARG, "source must be CLS_SRC_FACE_X0 or CLS_SRC_VOLUME");
     if (nbins < 1 || nbins > CLS_MAX_BINS) return fail(CLS_ERR_INVALID_ARG, "nbins out of [1, CLS_MAX_BINS]");
-    const uint32_t known = CLS_F_D1_SLAB | CLS_F_COLLISION_FLUX | CLS_F_FP32 | CLS_F_TRACE;
+    const uint32_t known = CLS_F_D1_SLAB | CLS_F_COLLISION_FLUX | CLS_F_FP32 | CLS_F_TRACE | CLS_F_TRACE_NO_BINS;
     if (flags & ~known) return fail(CLS_ERR_INVALID_ARG, "unknown flag bits");
     if ((flags & CLS_F_D1_SLAB) && d != 1) return fail(CLS_ERR_INVALID_ARG, "CLS_F_D1_SLAB requires d = 1");
-    if ((flags & CLS_F_TRACE) && (flags & CLS_F_FP32))
-        return fail(CLS_ERR_INVALID_ARG, "CLS_F_TRACE requires FP64 tracking");
+    if ((flags & CLS_F_TRACE_NO_BINS) && !(flags & CLS_F_TRACE))
+        return fail(CLS_ERR_INVALID_ARG, "CLS_F_TRACE_NO_BINS requires CLS_F_TRACE");
     uint32_t paper_bc = 0;
     if (d >= 2) paper_bc |= CLS_BC_FACE(2) | CLS_BC_FACE(3);
     if (d >= 3) paper_bc |= CLS_BC_FACE(4) | CLS_BC_FACE(5);

@@ -51,6 +51,14 @@ struct alignas(16) DevProblem {
     // FP32 flight-distance scales: a distance is log2(U) times -ln2 / Sigma_i
     // (collision) or -ln2 Lambda_i (interface)
     float dsigf[2], dlamf[2];
+    // Decisions on a uniform U = (k + 1/2) 2^-23 against a probability q are
+    // taken on the integer k: U < q exactly when the bit pattern of the float
+    // 1 + k 2^-23 is below 0x3F800000 + ceil(q 2^23 - 1/2). Both precisions
+    // then take the FP64 decision (scattering with c_i, source material with
+    // p_0) bit for bit.
+    uint32_t cthr[2];           // scattering, per material
+    uint32_t p0thr;             // source material 0
+    int32_t trace_bins;         // trace hash includes the bin of each event (else events and materials only)
     uint64_t seed;
     uint64_t histories;
     uint64_t chunk;             // histories per work item (batch)

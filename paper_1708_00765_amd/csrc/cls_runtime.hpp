@@ -84,6 +84,7 @@ uint64_t trace_count(const cls_problem *p, uint64_t histories);
 using sched::batch_chunk_size;
 using sched::chunk_size;
 using sched::grouped_chunk_size;
+uint32_t unit_threshold(double q);
 void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,
                       uint64_t trace_n, DevProblem *out);
 Variant variant_of(const cls_problem *p);

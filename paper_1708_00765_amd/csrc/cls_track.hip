@@ -135,13 +135,15 @@ static_assert(EV_LEAK_XHI - EV_LEAK_XHI == S_T && EV_LEAK_XHI - EV_LEAK_XLO == S
 // lane otherwise (a wave straddling two work chunks of different problems).
 template <typename R>
 struct Prm {
-    R p0, Lr, dxr;
+    R Lr, dxr;
     double Ld, inv_dx, dx;
     int K;
+    uint32_t p0thr;
     uint32_t key_lo, key_hi;
     uint64_t trace_n, max_steps;
     uint64_t *trace_hash;
     uint32_t *trace_len;
+    int trace_bins;
 };
 
 // The problem records are written by the host before the launch and only read
@@ -154,37 +156,43 @@ __device__ __forceinline__ Prm<R> load_prm(ConstProblem &P)
 {
     Prm<R> q;
     if constexpr (std::is_same<R, float>::value) {
-        q.p0 = P.p0f; q.Lr = P.Lf; q.dxr = P.dxf;
+        q.Lr = P.Lf; q.dxr = P.dxf;
     } else {
-        q.p0 = P.p0; q.Lr = P.L; q.dxr = P.dx;
+        q.Lr = P.L; q.dxr = P.dx;
     }
     q.Ld = P.L; q.inv_dx = P.inv_dx; q.dx = P.dx; q.K = P.nbins;
+    q.p0thr = P.p0thr;
     q.key_lo = (uint32_t)P.seed; q.key_hi = (uint32_t)(P.seed >> 32);
     q.trace_n = P.trace_n; q.max_steps = P.max_steps;
     q.trace_hash = P.trace_hash; q.trace_len = P.trace_len;
+    q.trace_bins = P.trace_bins;
     return q;
 }
 
 // Flight parameters of one material of a problem, kept per chunk slot in LDS
 // (written when the slot takes a chunk): the collision and interface distance
 // scales (FP32: -ln2 / Sigma_i and -ln2 Lambda_i, applied to log2 U; FP64:
-// 1 / Sigma_i and Lambda_i, applied to -ln U), the scattering ratio c_i and
-// 1 / Sigma_i. A flight reads its material's row with one LDS load instead of
-// selecting four values between the two materials.
+// 1 / Sigma_i and Lambda_i, applied to -ln U), 1 / Sigma_i and the integer
+// threshold of the scattering decision (see DevProblem::cthr). A flight reads
+// its material's row with one LDS load instead of selecting four values
+// between the two materials.
 template <typename R>
 struct alignas(16) MatRow {
-    R ds, dl, c, isig;
+    R ds, dl, isig;
+    uint32_t cthr;
 };
+static_assert(sizeof(MatRow<float>) == 16 && sizeof(MatRow<double>) == 32, "material rows of 16 / 32 bytes");
 
 template <typename R>
 __device__ __forceinline__ MatRow<R> mat_row(ConstProblem &P, int m)
 {
     MatRow<R> r;
     if constexpr (std::is_same<R, float>::value) {
-        r.ds = P.dsigf[m]; r.dl = P.dlamf[m]; r.c = P.cf[m]; r.isig = P.isigf[m];
+        r.ds = P.dsigf[m]; r.dl = P.dlamf[m]; r.isig = P.isigf[m];
     } else {
-        r.ds = P.isig[m]; r.dl = P.lam[m]; r.c = P.c[m]; r.isig = P.isig[m];
+        r.ds = P.isig[m]; r.dl = P.lam[m]; r.isig = P.isig[m];
     }
+    r.cthr = P.cthr[m];
     return r;
 }
 
@@ -193,11 +201,12 @@ __device__ __forceinline__ MatRow<R> mat_row(ConstProblem &P, int m)
 // at y = L when u_y > 0, at y = 0 otherwise), which is all that the flight
 // needs: the distance to that face is dy / |u_y|, a flight of length s takes
 // s |u_y| off it, a mirror reflection resets it to L, and a new direction
-// whose u_y has the other sign turns it into L - dy.
+// whose u_y has the other sign turns it into L - dy. Positions (x and these
+// distances) are FP64 in both tracking precisions.
 template <typename R>
 struct Lane {
     double x;
-    R dy, dz;                // distance along y / z to the face headed for
+    double dy, dz;           // distance along y / z to the face headed for
     R ux, uy, uz;
     R iux, aiuy, aiuz, ig;   // 1/u_x, |1/u_y|, |1/u_z|, 1/(chord factor)
     R fx;                    // x inside its flux bin, in bin widths (FP32 track-length)
@@ -232,6 +241,10 @@ __device__ __forceinline__ int bin_of(double x, double inv_dx, int K, R *frac)
     return k;
 }
 
+// U < 1/2 as an integer test on the uniform's bit pattern (see
+// DevProblem::cthr): k < 2^22.
+constexpr uint32_t kHalfThr = 0x3FC00000u;
+
 // One event step of one lane: the source (step 0) or a flight. Returns the
 // event code. `tal` is the lane's LDS tally buffer.
 template <int G, int EST, int SRC, bool FP32, bool TRACE, typename R>
@@ -250,7 +263,7 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         // Lateral coordinates go into dy / dz with u_y = u_z = -1 standing for
         // "heading for the face at 0"; the direction sampler below converts
         // them to distances to the faces the sampled direction heads for.
-        L.m = (unit<R>(B.k[0]) < P.p0) ? 0 : 1;
+        L.m = B.k[0] < P.p0thr ? 0 : 1;
         L.x = 0.0; L.dy = 0; L.dz = 0;
         L.uy = (R)-1; L.uz = (R)-1;
         if (SRC == SRC_FACE) {
@@ -264,20 +277,20 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
                 need_dir = true; src_dir = true;
                 cos_t = MM::sqrt_(unit<R>(B.k[1]));
                 turns = unit<R>(B.k[2]);
-                L.dy = P.Lr * unit<R>(B.k[3]);
-                if (G == GEOM_CUBE3D) L.dz = P.Lr * unit<R>(B.k[4]);
+                L.dy = P.Ld * unit<double>(B.k[3]);
+                if (G == GEOM_CUBE3D) L.dz = P.Ld * unit<double>(B.k[4]);
             }
         } else {
             L.x = P.Ld * (double)unit<R>(B.k[1]);
             if (G == GEOM_ROD) {
-                L.ux = unit<R>(B.k[2]) < (R)0.5 ? (R)1 : (R)-1;
+                L.ux = B.k[2] < kHalfThr ? (R)1 : (R)-1;
                 L.iux = L.ux;
             } else if (G == GEOM_SLAB) {
                 L.ux = (R)2 * unit<R>(B.k[2]) - (R)1;
                 L.iux = MM::rcp(L.ux);
                 L.ig = MM::abs_(L.iux);
             } else if (G == GEOM_EXT2D) {
-                L.dy = P.Lr * unit<R>(B.k[2]);
+                L.dy = P.Ld * unit<double>(B.k[2]);
                 need_dir = true;
                 cos_t = (R)2 * unit<R>(B.k[3]) - (R)1;
                 turns = unit<R>(B.k[4]);
@@ -285,9 +298,9 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
                 need_dir = true;
                 cos_t = (R)2 * unit<R>(B.k[2]) - (R)1;
                 turns = unit<R>(B.k[3]);
-                L.dy = P.Lr * unit<R>(B.k[4]);
+                L.dy = P.Ld * unit<double>(B.k[4]);
                 const Block5 B2 = philox_u23(0u, 1u, L.h, P.key_lo, P.key_hi);
-                L.dz = P.Lr * unit<R>(B2.k[0]);
+                L.dz = P.Ld * unit<double>(B2.k[0]);
             }
         }
         if (SRC == SRC_FACE) {
@@ -297,10 +310,10 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
             L.kcur = bin_of<R>(L.x, P.inv_dx, P.K, &L.fx);
         }
         ev = EV_SOURCE;
-        if (TRACE) L.hash = fnv_event(L.hash, EV_SOURCE, L.m, L.kcur);
+        if (TRACE) L.hash = fnv_event(L.hash, EV_SOURCE, L.m, P.trace_bins ? L.kcur : 0);
     } else if ((uint64_t)L.step > P.max_steps) {
         ev = EV_CAP;
-        if (TRACE) L.hash = fnv_event(L.hash, EV_CAP, L.m, L.kcur);
+        if (TRACE) L.hash = fnv_event(L.hash, EV_CAP, L.m, P.trace_bins ? L.kcur : 0);
     } else {
         // ---- flight: three distances, the smallest wins (Section 4) ----
         const int mf = L.m;
@@ -316,12 +329,12 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         // axis index: the event tests below use them directly)
         bool ny = false, nz = false;
         if (AXES >= 2) {
-            const R l = L.dy * L.aiuy;
+            const R l = (R)L.dy * L.aiuy;
             ny = l < lb;
             lb = ny ? l : lb;
         }
         if (AXES >= 3) {
-            const R l = L.dz * L.aiuz;
+            const R l = (R)L.dz * L.aiuz;
             nz = l < lb;
             lb = nz ? l : lb;
         }
@@ -332,12 +345,20 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         // NaN face distance never wins), so the FP32 clamp at 0 is an integer
         // max of the bit pattern (negative floats are negative integers)
         if (FP32) s = __int_as_float(max(__float_as_int(s), 0));
+        const double sd = (double)s;
         const double xa = L.x;
         const int ka0 = L.kcur;
         const R fa = L.fx;
-        L.x += (double)(s * L.ux);
-        if (AXES >= 2) L.dy = MM::fma_(-s, MM::abs_(L.uy), L.dy);
-        if (AXES >= 3) L.dz = MM::fma_(-s, MM::abs_(L.uz), L.dz);
+        if (FP32) L.x = __builtin_fma(sd, (double)L.ux, L.x);
+        else L.x += s * L.ux;
+        // FP32 tracking moves the FP64 positions by the exact FP64 product of
+        // the FP32 flight length and direction (no rounding beyond the add):
+        // lateral coordinates rounded to FP32 drifted by up to 3e-7 per
+        // flight, enough to change which of a lateral face and a collision
+        // comes first in about 2.6e-5 of the 98-flight histories of optically
+        // thick cubes; in FP64 that is 2.4e-6
+        if (AXES >= 2) L.dy = __builtin_fma(-sd, (double)MM::abs_(L.uy), L.dy);
+        if (AXES >= 3) L.dz = __builtin_fma(-sd, (double)MM::abs_(L.uz), L.dz);
         // FP64 puts a leaking particle exactly on its face; in FP32 the
         // history ends there anyway and the snap would only move the last
         // track-length partial by a rounding error
@@ -353,7 +374,6 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         // same update with pa = s and full = pb = 0, so every flight issues
         // the same four adds.
         if (EST == EST_TRACK) {
-            const double sd = (double)s;
             L.tscore += sd;
             // s >= 0, so x moves with the sign of u_x (a move that rounds to
             // zero stays in its bin, where the orientation does not matter)
@@ -392,7 +412,7 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         const bool refl_y = AXES >= 2 && bnd && ny && !nz;
         const bool refl_z = AXES >= 3 && bnd && nz;
         const bool intf = !bnd && !coll;
-        const bool scat = coll && unit<R>(B.k[2]) < mat.c;
+        const bool scat = coll && B.k[2] < mat.cthr;
         if (EST == EST_COLLISION) {
             if (coll) {
                 lds_add(tal + L.kcur, (double)mat.isig);
@@ -413,15 +433,15 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         // distance L from the face it now heads for
         if (AXES >= 2) {
             L.uy = refl_y ? -L.uy : L.uy;
-            L.dy = refl_y ? P.Lr : L.dy;
+            L.dy = refl_y ? P.Ld : L.dy;
         }
         if (AXES >= 3) {
             L.uz = refl_z ? -L.uz : L.uz;
-            L.dz = refl_z ? P.Lr : L.dz;
+            L.dz = refl_z ? P.Ld : L.dz;
         }
         // isotropic scattering: a new direction
         if (G == GEOM_ROD) {
-            const R nu = unit<R>(B.k[3]) < (R)0.5 ? (R)1 : (R)-1;
+            const R nu = B.k[3] < kHalfThr ? (R)1 : (R)-1;
             L.ux = scat ? nu : L.ux;
             L.iux = L.ux;
         } else if (G == GEOM_SLAB) {
@@ -438,7 +458,7 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         L.n_int += (uint32_t)intf;
         L.n_scat += (uint32_t)scat;
         if (AXES >= 2) L.n_lat += (uint32_t)(refl_y || refl_z);
-        if (TRACE) L.hash = fnv_event(L.hash, ev, mf, L.kcur);
+        if (TRACE) L.hash = fnv_event(L.hash, ev, mf, P.trace_bins ? L.kcur : 0);
     }
     // ---- shared direction sampler: polar axis x for the inward cosine-law
     //      source, z for isotropic emission ----
@@ -452,12 +472,12 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         R nx, ny, nz;
         if (src_dir) { nx = cos_t; ny = a; nz = b; }
         else { nx = a; ny = b; nz = cos_t; }
-        if ((ny > 0) != (L.uy > 0)) L.dy = P.Lr - L.dy;
+        if ((ny > 0) != (L.uy > 0)) L.dy = P.Ld - L.dy;
         L.ux = nx; L.uy = ny;
         L.iux = MM::rcp(nx);
         L.aiuy = MM::rcp(MM::abs_(ny));
         if (G == GEOM_CUBE3D) {
-            if ((nz > 0) != (L.uz > 0)) L.dz = P.Lr - L.dz;
+            if ((nz > 0) != (L.uz > 0)) L.dz = P.Ld - L.dz;
             L.aiuz = MM::rcp(MM::abs_(nz));
         }
         L.uz = nz;
@@ -875,7 +895,7 @@ typedef void (*TrackFn)(TrackArgs);
 template <int G, int EST, int SRC>
 static TrackFn pick_prec(const Variant &v)
 {
-    if (v.fp32) return track_kernel<G, EST, SRC, true, false>;
+    if (v.fp32) return v.trace ? track_kernel<G, EST, SRC, true, true> : track_kernel<G, EST, SRC, true, false>;
     if (v.trace) return track_kernel<G, EST, SRC, false, true>;
     return track_kernel<G, EST, SRC, false, false>;
 }

@@ -49,7 +49,7 @@ GOOD = dict(d=3, L=10.0, sigma_t=(0.5, 1.0), c=(0.2, 0.9), lam=(1.0, 0.3))
     dict(lam=(0.0, 1.0)), dict(lam=(math.inf, 1.0)),
     dict(source=2), dict(nbins=0), dict(nbins=2049), dict(flags=1 << 7),
     dict(flags=1),                      # slab flag with d = 3
-    dict(flags=(1 << 2) | (1 << 3)),    # trace needs FP64
+    dict(flags=1 << 4),                 # event-only trace hash without a trace
     dict(boundaries=0),                 # vacuum lateral faces
     dict(boundaries=0b111111 | 1),      # reflecting x-face
 ])
