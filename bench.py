@@ -2,16 +2,20 @@
 """Throughput of Chord Length Sampling (Algorithm A, arXiv 1708.00765 Section 4)
 on one MI355X.
 
-Default workload (cube3d_track): d=3 cube of side 10, vacuum x-faces, mirroring
-lateral faces, cosine-weighted incidence on x=0; 8 seeded parameter sets
-(Sigma_i log-uniform in [0.02, 2], c_i uniform in [0, 1], Lambda_i log-uniform
-in [0.1, 10]); 1e8 histories per set; 200 x-bins with the track-length
-estimator. A step runs all 8 sets in one batched persistent launch with FP32
-flight arithmetic and FP64 tallies, then finalizes and copies the results back.
+Default workload (stress3d, the divergence-stress configuration): d=3 cube of side
+10, vacuum x-faces, mirroring lateral faces, cosine-weighted incidence on x=0; 32
+seeded parameter sets in the high-scattering, optically thick regime (c_i uniform in
+[0.99, 0.999], Sigma_i log-uniform in [0.5, 5], Lambda_i log-uniform in [0.05, 1]);
+1e8 histories per set; 1000 x-bins with the track-length estimator. A step runs all
+32 sets in one batched persistent launch with FP32 flight arithmetic, FP64 positions
+and FP64 tallies, then finalizes and copies the results back.
 
-Also reported: the plain FP64 one-problem-per-launch rate on the same sets, the
-roofline of the tracking kernel (VALU issue slots, see perf_model.py) and the
-FP64 CPU oracle on a bounded sample of the same sets.
+Also reported: the plain FP64 one-problem-per-launch rate on the same sets and the
+FP32 form's deviation from it on the same random streams (the acceptance rule of the
+FP32 form), the roofline of the tracking kernel (VALU issue slots, see perf_model.py),
+the FP64 CPU oracle on a bounded sample of the same sets (and each set's FP32 result
+against that oracle sample in combined standard deviations), the cube3d and extruded
+2D workloads, the quenched d = 1 kernel and the served Poisson request stream.
 
 Prints one JSON line.
 """
@@ -68,11 +72,11 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per tracking launch of this workload from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
-    sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "track_kernel_cube3d_track_traffic.md")
+def measured_traffic(workload_name):
+    """HBM bytes per tracking launch of a workload from its committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"track_kernel_{workload_name}_traffic.md")
     if not os.path.exists(path):
         return None
     keys = {}
@@ -85,38 +89,70 @@ def measured_traffic():
     return float(keys["traffic_bytes_per_launch"])
 
 
-def crn_deviation(full32, full64):
-    """FP32 vs FP64 tallies of the same histories (common random numbers): the
-    largest relative deviation over the sets of T, R and the total flux, of the
-    flux profile as a whole (L2 norm of the bin differences over that of the
-    FP64 bins), of the worst single bin, the share of the total flux carried by
-    bins deviating by more than 1e-4, and the largest deviation in FP64 standard
-    deviations. The per-bin figures take the populated bins, those holding at
-    least 1e-3 of the set's largest bin: a rounding-order flip sends one history
-    elsewhere, and in a bin that the FP64 run barely touched (a sliver of one
-    track, with a sigma to match) that single history reads as an enormous
-    relative or sigma deviation while the profile agrees."""
+# Acceptance rule of the FP32 form (fixed before it was measured), per parameter set,
+# with x32 / x64 the FP32 / FP64 results on the same random streams and sigma64 the
+# FP64 one-sigma error: (1) T, R, A and the total flux within 1e-4 relative; (2) the
+# flux profile within 1e-4 in L2 norm; (3) every bin within 1e-4 relative plus a tenth
+# of the bin's FP64 sigma. No set and no bin is left out.
+RULE_REL = 1e-4
+RULE_SIGMA_SHARE = 0.1
+
+
+def fp32_acceptance(full32, full64):
+    """Evaluate the acceptance rule over all sets: worst values and violation counts."""
     import numpy as np
-    rel_s = rel_b = rel_l2 = sig = share = 0.0
+    worst_s = worst_p = worst_b = worst_sig = 0.0
+    v_s = v_p = v_b = 0
     for (t32, f32, _), (t64, f64, s64) in zip(full32, full64):
-        for k, sk in (("T", "sigma_T"), ("R", "sigma_R"), ("total_flux", "sigma_total_flux")):
+        for k, sk in (("T", "sigma_T"), ("R", "sigma_R"), ("A", "sigma_A"), ("total_flux", "sigma_total_flux")):
             a, b, sg = getattr(t64, k), getattr(t32, k), getattr(t64, sk)
-            if a != 0.0:
-                rel_s = max(rel_s, abs(b - a) / abs(a))
+            r = abs(b - a) / abs(a) if a != 0.0 else (0.0 if b == a else float("inf"))
+            worst_s = max(worst_s, r)
+            v_s += r > RULE_REL
             if sg > 0.0:
-                sig = max(sig, abs(b - a) / sg)
-        nz = np.abs(f64) >= 1e-3 * np.abs(f64).max() if np.any(f64) else np.zeros(f64.shape, bool)
-        if nz.any():
-            rb = np.abs(f32[nz] - f64[nz]) / np.abs(f64[nz])
-            rel_b = max(rel_b, float(rb.max()))
-            share = max(share, float(np.abs(f64[nz][rb > 1e-4]).sum() / np.abs(f64).sum()))
-            rel_l2 = max(rel_l2, float(np.linalg.norm(f32 - f64) / np.linalg.norm(f64)))
-        ok = nz & (s64 > 0.0)
+                worst_sig = max(worst_sig, abs(b - a) / sg)
+        n64 = float(np.linalg.norm(f64))
+        if n64 > 0.0:
+            r = float(np.linalg.norm(f32 - f64)) / n64
+            worst_p = max(worst_p, r)
+            v_p += r > RULE_REL
+        bound = RULE_REL * np.abs(f64) + RULE_SIGMA_SHARE * s64
+        diff = np.abs(f32 - f64)
+        v_b += int(np.sum(diff > bound))
+        ok = bound > 0
         if ok.any():
-            sig = max(sig, float(np.max(np.abs(f32[ok] - f64[ok]) / s64[ok])))
-    return {"max_rel_scalar": rel_s, "max_rel_profile_l2": rel_l2, "max_rel_bin": rel_b,
-            "flux_share_of_bins_beyond_1e-4": share, "max_sigma": sig,
-            "compared": "T, R and total flux of each set; the flux bins holding at least 1e-3 of the set's largest"}
+            worst_b = max(worst_b, float(np.max(diff[ok] / bound[ok])))
+    return {"max_rel_scalar": worst_s, "max_rel_profile_l2": worst_p, "max_bin_deviation_over_allowance": worst_b,
+            "max_scalar_deviation_in_fp64_sigma": worst_sig,
+            "violations": {"scalars": v_s, "profiles": v_p, "bins": v_b},
+            "bins_compared": int(sum(len(f[1]) for f in full64)),
+            "passes": v_s == 0 and v_p == 0 and v_b == 0,
+            "rule": "per set: T, R, A, total flux within 1e-4 relative; flux profile within 1e-4 (L2); "
+                    "every bin within 1e-4 relative + 0.1 FP64 sigma; FP32 vs FP64 on the same streams"}
+
+
+def oracle_agreement(full32, oracle_results):
+    """Each set's FP32 GPU result against the FP64 oracle on independent streams, in
+    combined standard deviations: the worst |z| of T, R, A and the total flux, and the
+    flux bins beyond 4 sigma against the 0.999 quantile of Binomial(bins, 6.3e-5)."""
+    import numpy as np
+    from scipy.stats import binom
+    zmax = 0.0
+    beyond = bins = 0
+    for (t, f, fs), o in zip(full32, oracle_results):
+        for a, sa, b, sb in ((t.T, t.sigma_T, o.T, o.sigma_T), (t.R, t.sigma_R, o.R, o.sigma_R),
+                             (t.A, t.sigma_A, o.A, o.sigma_A),
+                             (t.total_flux, t.sigma_total_flux, o.total_flux, o.total_flux_sigma)):
+            sc = (sa * sa + sb * sb) ** 0.5
+            if sc > 0:
+                zmax = max(zmax, abs(a - b) / sc)
+        sc = np.hypot(fs, o.flux_sigma)
+        ok = sc > 0
+        beyond += int(np.sum(np.abs(f[ok] - o.flux[ok]) / sc[ok] > 4.0))
+        bins += int(ok.sum())
+    return {"max_abs_z_scalars": zmax, "bins_beyond_4_sigma": beyond, "bins": bins,
+            "bins_beyond_4_sigma_allowed": int(binom.ppf(0.999, max(bins, 1), 6.334e-5)),
+            "oracle_histories_per_set": int(oracle_results[0].histories) if oracle_results else 0}
 
 
 def load_paper_rows():
@@ -325,18 +361,25 @@ def run_ext2d_comparison(cls, torch, stream, steps):
             cls.cls_run(p, min(s.histories, 10000), s.seed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        full64 = None
         for k in range(steps):
             for p, s in zip(p64, specs):
                 cls.cls_run(p, s.histories, s.seed + k + 1)
+            if k == 0:
+                full64 = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(p64, specs)]
         torch.cuda.synchronize()
         w64 = (time.perf_counter() - t0) / steps
+        # the FP32 batched form on the seeds of the first FP64 pass (same streams)
+        cls.cls_run_batch(p32, hist, [s.seed + 1 for s in specs])
+        full32 = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(p32, specs)]
     finally:
         for p in p32 + p64:
             cls.cls_destroy_problem(p)
     return {"sets": len(specs), "histories": total, "fp32_batched_value": total / w32,
             "fp64_plain_value": total / w64, "ratio": w64 / w32, "fp32_batched_ms": 1e3 * w32,
             "fp64_plain_ms": 1e3 * w64, "unit": "histories/s", "autotuned_config": cfg,
-            "fp32_batched_default_config_value": total / w_default}
+            "fp32_batched_default_config_value": total / w_default,
+            "fp32_vs_fp64_same_streams": fp32_acceptance(full32, full64)}
 
 
 def run_served(cls, seconds, rate):
@@ -420,18 +463,114 @@ def run_served_saturated(cls, rate, seconds):
                         f"{rate:g} requests/s submitted at once"}
 
 
+def physical_cpu():
+    """CPU model and physical core count of this host (from /proc/cpuinfo)."""
+    model, cores = "", set()
+    phys = core = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name" and not model:
+                model = v
+            elif k == "physical id":
+                phys = v
+            elif k == "core id":
+                core = v
+            elif not k and phys is not None and core is not None:
+                cores.add((phys, core))
+                phys = core = None
+        if phys is not None and core is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return model, (len(cores) or None)
+
+
+def run_form(cls, torch, stream, perf_model, specs, steps, warmup, fp64_steps, label):
+    """One workload: `steps` timed batched FP32 launches (after `warmup`), then the
+    plain FP64 one-problem-per-launch runs, the first of them on the seeds of the last
+    timed FP32 step (common random numbers: the acceptance rule of the FP32 form)."""
+    total_hist = sum(s.histories for s in specs)
+    geom = specs[0].geom_name
+    probs = [make_problem(cls, s, fp32=True) for s in specs]
+    for p in probs:
+        cls.cls_set_stream(p, stream)
+    log(f"{label}: fp32 batched, {len(specs)} sets x {_span(s.histories for s in specs)} histories, "
+        f"{warmup} warmup + {steps} steps")
+    try:
+        wall, track_ms, full32 = run_batch_steps(cls, torch, probs, specs, steps, warmup, 0)
+    finally:
+        for p in probs:
+            cls.cls_destroy_problem(p)
+    tallies = [f[0] for f in full32]
+    last_step = warmup + steps - 1
+    value = total_hist * steps / wall
+    flights = sum(t.flights for t in tallies)
+    collisions = sum(t.collisions for t in tallies)
+    scatters = sum(t.scatters for t in tallies)
+    lateral = sum(t.lateral_reflections for t in tallies)
+    kernel_ms = track_ms / steps
+    slots = perf_model.algorithmic_slots(geom, total_hist, flights, scatters, lateral, fp32=True,
+                                         track=not specs[0].collision)
+    achieved = slots / (kernel_ms * 1e-3) / 1e12
+    peak = perf_model.PEAK_SLOTS_PER_S / 1e12
+    out = {"value": value, "unit": "histories/s", "ms_per_step": 1e3 * wall / steps, "kernel_ms": kernel_ms,
+           "collisions_per_s": collisions * steps / wall, "flights_per_s": flights * steps / wall,
+           "flights_per_history": flights / total_hist, "histories_per_step": total_hist,
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
+                        "frac": achieved / peak, "kernel_ms": kernel_ms, "algorithmic_slots_per_launch": slots}}
+    log(f"  {out['ms_per_step']:.1f} ms/step, kernel {kernel_ms:.1f} ms, {value:.4g} hist/s, "
+        f"{flights / total_hist:.2f} flights/hist, {achieved:.2f}/{peak:.2f} Tslot/s (frac {achieved / peak:.3f})")
+    if fp64_steps > 0:
+        probs64 = [make_problem(cls, s, fp32=False) for s in specs]
+        try:
+            for p in probs64:
+                cls.cls_set_stream(p, stream)
+            for p, s in zip(probs64, specs):           # warm the FP64 code object
+                cls.cls_run(p, min(s.histories, 100_000), s.seed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k64 = 0.0
+            full64 = None
+            for k in range(fp64_steps):
+                for p, s in zip(probs64, specs):
+                    cls.cls_run(p, s.histories, (s.seed + 0x9E3779B97F4A7C15 * (last_step + k)) & (2**64 - 1))
+                    k64 += cls.cls_read_tallies(p, s.nbins)[0].track_ms
+                if k == 0:
+                    full64 = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(probs64, specs)]
+            torch.cuda.synchronize()
+            w64 = time.perf_counter() - t0
+        finally:
+            for p in probs64:
+                cls.cls_destroy_problem(p)
+        v64 = total_hist * fp64_steps / w64
+        out["fp64_plain"] = {"value": v64, "unit": "histories/s", "ms_per_step": 1e3 * w64 / fp64_steps,
+                             "kernel_ms_per_step": k64 / fp64_steps, "launches_per_step": len(specs)}
+        out["speedup_vs_fp64_plain"] = value / v64
+        acc = fp32_acceptance(full32, full64)
+        out["fp32_vs_fp64_same_streams"] = acc
+        log(f"  fp64 plain: {1e3 * w64 / fp64_steps:.1f} ms/step, {v64:.4g} hist/s, FP32/FP64 {value / v64:.2f}x; "
+            f"FP32 vs FP64 (same streams): scalars {acc['max_rel_scalar']:.2e}, profile "
+            f"{acc['max_rel_profile_l2']:.2e}, worst bin {acc['max_bin_deviation_over_allowance']:.3f} of its "
+            f"allowance, violations {acc['violations']} -> {'passes' if acc['passes'] else 'FAILS'}")
+    return out, full32
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cube3d_track")
+    ap.add_argument("--workload", default="stress3d")
     ap.add_argument("--histories", type=int, default=0, help="override histories per set")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed passes of the FP64 plain leg (0 = skip)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0, help="oracle sample budget (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--serve-seconds", type=float, default=15.0,
+    ap.add_argument("--cube3d-steps", type=int, default=3,
+                    help="timed steps of the cube3d_track leg (8 sets x 1e8, 200 bins; 0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served Poisson request stream (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="request arrival rate (1/s)")
     ap.add_argument("--saturate-seconds", type=float, default=2.0,
@@ -469,71 +608,24 @@ def main() -> int:
     total_hist = sum(s.histories for s in specs)
     geom = specs[0].geom_name
 
-    # ---- FP32 batched: the timed steps ----------------------------------
-    probs = [make_problem(cls, s, fp32=True) for s in specs]
-    for p in probs:
-        cls.cls_set_stream(p, stream)
-    log(f"fp32 batched: {len(specs)} sets x {specs[0].histories:.3g} histories, "
-        f"{args.warmup} warmup + {args.steps} steps")
-    wall, track_ms, full32 = run_batch_steps(cls, torch, probs, specs, args.steps, args.warmup, 0)
-    tallies = [f[0] for f in full32]
-    last_step = args.warmup + args.steps - 1      # seed index of the last timed FP32 step
-    ms_per_step = 1e3 * wall / args.steps
-    value = total_hist * args.steps / wall
-    flights = sum(t.flights for t in tallies)
-    collisions = sum(t.collisions for t in tallies)
-    scatters = sum(t.scatters for t in tallies)
-    lateral = sum(t.lateral_reflections for t in tallies)
-    kernel_ms = track_ms / args.steps
-    slots = perf_model.algorithmic_slots(geom, total_hist, flights, scatters, lateral, fp32=True,
-                                         track=not specs[0].collision)
-    achieved = slots / (kernel_ms * 1e-3) / 1e12
-    peak = perf_model.PEAK_SLOTS_PER_S / 1e12
-    log(f"  {ms_per_step:.1f} ms/step, kernel {kernel_ms:.1f} ms, {value:.4g} hist/s, "
-        f"{flights / total_hist:.2f} flights/hist, {achieved:.2f}/{peak:.2f} Tslot/s")
-    for p in probs:
-        cls.cls_destroy_problem(p)
-
-    # ---- FP64 plain: one problem per launch ----------------------------------
-    fp64 = None
-    if args.fp64_steps > 0:
-        probs64 = [make_problem(cls, s, fp32=False) for s in specs]
-        for p in probs64:
-            cls.cls_set_stream(p, stream)
-        for p, s in zip(probs64, specs):           # warm the FP64 code object
-            cls.cls_run(p, min(s.histories, 100_000), s.seed)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        k64 = 0.0
-        full64 = None
-        for k in range(args.fp64_steps):
-            # the first pass uses the seeds of the last timed FP32 step: common
-            # random numbers, so the two results differ only by the precision
-            for p, s in zip(probs64, specs):
-                cls.cls_run(p, s.histories, (s.seed + 0x9E3779B97F4A7C15 * (last_step + k)) & (2**64 - 1))
-                k64 += cls.cls_read_tallies(p, s.nbins)[0].track_ms
-            if k == 0:
-                full64 = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(probs64, specs)]
-        torch.cuda.synchronize()
-        w64 = time.perf_counter() - t0
-        v64 = total_hist * args.fp64_steps / w64
-        fp64 = {"value": v64, "unit": "histories/s", "ms_per_step": 1e3 * w64 / args.fp64_steps,
-                "kernel_ms_per_step": k64 / args.fp64_steps, "launches_per_step": len(specs)}
-        fp64["fp32_deviation"] = crn_deviation(full32, full64)
-        log(f"fp64 plain: {fp64['ms_per_step']:.1f} ms/step, {v64:.4g} hist/s; fp32 vs fp64 (same seeds): "
-            f"max rel dev T/R/flux {fp64['fp32_deviation']['max_rel_scalar']:.2e}, "
-            f"profile L2 {fp64['fp32_deviation']['max_rel_profile_l2']:.2e}, "
-            f"worst bin {fp64['fp32_deviation']['max_rel_bin']:.2e} "
-            f"(bins beyond 1e-4 carry {fp64['fp32_deviation']['flux_share_of_bins_beyond_1e-4']:.2e} of the flux), "
-            f"{fp64['fp32_deviation']['max_sigma']:.2f} sigma")
-        for p in probs64:
-            cls.cls_destroy_problem(p)
+    # ---- the main workload: FP32 batched (timed steps) vs FP64 plain ----------
+    main_leg, full32 = run_form(cls, torch, stream, perf_model, specs, args.steps, args.warmup, args.fp64_steps,
+                                args.workload)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+
+    # ---- cube3d_track: 8 sets x 1e8, 200 bins ----------------------------------
+    cube = None
+    if args.cube3d_steps > 0 and args.workload != "cube3d_track":
+        cube, _ = run_form(cls, torch, stream, perf_model, workload("cube3d_track"), args.cube3d_steps, 1,
+                           1, "cube3d_track")
+        cube["workload"] = ("cube3d_track: 8 sets x 1e8 histories, d=3 cube, L=10, 200 x-bins, track-length flux, "
+                            "Sigma_i log-uniform [0.02, 2], c_i uniform [0, 1], Lambda_i log-uniform [0.1, 10]")
+        cube["traffic"] = measured_traffic("cube3d_track")
 
     # ---- 256 uneven ext2d sets: one batched FP32 launch vs one FP64 launch per set --
     ext2d = None
@@ -598,14 +690,15 @@ def main() -> int:
             with open(base + "_ref" + (ext or ".json"), "w") as f:
                 json.dump({"summary": paper_ref, "rows": rows}, f, indent=1)
 
-    # ---- CPU oracle on a bounded sample ---------------------------------------
+    # ---- CPU oracle on a bounded sample of the main workload -------------------
     cpu = None
+    oracle_vs = None
     if args.cpu_seconds > 0:
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         from oracle import oracle
         from helpers import run_oracle
         # calibrate on a sample large enough that thread start-up does not dominate
-        per = 20000
+        per = 2000
         while True:
             t0 = time.perf_counter()
             for s in specs:
@@ -617,44 +710,50 @@ def main() -> int:
         n_each = max(per, int(per * args.cpu_seconds / max(cal, 1e-6)))
         t0 = time.perf_counter()
         coll = 0
+        orc = []
         for s in specs:
-            coll += run_oracle(s, histories=n_each, seed=s.seed + 11).collisions
+            r = run_oracle(s, histories=n_each, seed=s.seed + 11)
+            coll += r.collisions
+            orc.append(r)
         tc = time.perf_counter() - t0
         # one thread on a sample a tenth of the size (histories are independent,
         # so rates extrapolate linearly)
-        n_one = max(1000, n_each // (10 * max(1, oracle.max_threads())))
+        n_one = max(100, n_each // (10 * max(1, oracle.max_threads())))
         t1 = time.perf_counter()
         for s in specs:
             run_oracle(s, histories=n_one, seed=s.seed + 13, threads=1)
         t1 = time.perf_counter() - t1
-        cpu_model = ""
-        try:
-            for line in open("/proc/cpuinfo"):
-                if line.startswith("model name"):
-                    cpu_model = line.split(":", 1)[1].strip()
-                    break
-        except OSError:
-            pass
+        cpu_model, phys = physical_cpu()
         cpu = {"value": n_each * len(specs) / tc, "unit": "histories/s", "cores": oracle.max_threads(),
                "kind": "oracle",
                "sample": f"the {len(specs)} {args.workload} parameter sets x {n_each} histories each "
-                         f"({tc:.1f} s, FP64, OpenMP over 4096-history chunks)",
+                         f"({tc:.1f} s, FP64, OpenMP over 4096-history chunks, {oracle.max_threads()} threads)",
                "collisions_per_s": coll / tc,
                "single_thread_value": n_one * len(specs) / t1,
                "single_thread_sample": f"{len(specs)} sets x {n_one} histories ({t1:.1f} s, 1 thread)",
-               "cpu_model": cpu_model, "logical_cpus": os.cpu_count()}
+               "cpu_model": cpu_model, "physical_cores": phys, "logical_cpus": os.cpu_count()}
         log(f"cpu oracle: {cpu['value']:.4g} hist/s on {cpu['cores']} threads "
-            f"({cpu['single_thread_value']:.4g} on 1 thread; {cpu_model})")
+            f"({cpu['single_thread_value']:.4g} on 1 thread; {cpu_model}, {phys} physical cores)")
+        # the same oracle runs are the FP64 reference of the FP32 results (independent streams)
+        oracle_vs = oracle_agreement(full32, orc)
+        log(f"fp32 batched vs the FP64 oracle ({n_each} histories per set): max |z| {oracle_vs['max_abs_z_scalars']:.2f}, "
+            f"bins beyond 4 sigma {oracle_vs['bins_beyond_4_sigma']} of {oracle_vs['bins']} "
+            f"(allowed {oracle_vs['bins_beyond_4_sigma_allowed']})")
 
-    traffic = measured_traffic() if args.workload == "cube3d_track" and not args.histories else None
+    traffic = measured_traffic(args.workload) if not args.histories else None
+    kernel_ms = main_leg["kernel_ms"]
+    roof = dict(main_leg["roofline"])
+    roof.update({"traffic": traffic,
+                 "traffic_unit": "HBM bytes per tracking launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                 "traffic_gb_per_s": (traffic / (kernel_ms * 1e-3) / 1e9) if traffic else None})
     line = {
         "metric": "histories/s on 1 MI355X, FP32-batched vs plain FP64 CLS; p50/p99 req latency",
-        "value": value,
+        "value": main_leg["value"],
         "unit": "histories/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -663,19 +762,18 @@ def main() -> int:
         "config": {"workload": f"{args.workload}: {len(specs)} sets x {_span(s.histories for s in specs)} histories, "
                                f"d={specs[0].d} ({geom}), L={specs[0].L:g}, {_span(s.nbins for s in specs)} x-bins, "
                                f"{'collision' if specs[0].collision else 'track-length'} flux, "
-                               "FP32 tracking with FP64 tallies, one batched persistent launch per step",
+                               "FP32 tracking with FP64 positions and tallies, one batched persistent launch per step",
                    "sets": len(specs), "histories_per_step": total_hist},
-        "collisions_per_s": collisions * args.steps / wall,
-        "flights_per_s": flights * args.steps / wall,
-        "flights_per_history": flights / total_hist,
-        "fp64_plain": fp64,
-        "speedup_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     "traffic_unit": "HBM bytes per tracking launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-                     "traffic_gb_per_s": (traffic / (kernel_ms * 1e-3) / 1e9) if traffic else None,
-                     "kernel_ms": kernel_ms, "algorithmic_slots_per_launch": slots},
+        "collisions_per_s": main_leg["collisions_per_s"],
+        "flights_per_s": main_leg["flights_per_s"],
+        "flights_per_history": main_leg["flights_per_history"],
+        "fp64_plain": main_leg.get("fp64_plain"),
+        "speedup_vs_fp64_plain": main_leg.get("speedup_vs_fp64_plain"),
+        "fp32_vs_fp64_same_streams": main_leg.get("fp32_vs_fp64_same_streams"),
+        "fp32_vs_oracle": oracle_vs,
+        "roofline": roof,
         "cpu_baseline": cpu,
+        "cube3d_track": cube,
         "served": served,
         "served_saturated": served_sat,
         "ext2d_batched_vs_fp64_plain": ext2d,

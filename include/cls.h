@@ -133,7 +133,8 @@ cls_status cls_set_trace_histories(cls_problem *p, uint64_t n);
  * on the problem's stream and returns at once (poll with cls_query).
  * Errors: CLS_ERR_INVALID_ARG (histories == 0), CLS_ERR_NO_DEVICE,
  * CLS_ERR_DEVICE, CLS_ERR_OUT_OF_MEMORY, CLS_ERR_EVENT_CAP (reported by
- * cls_run / cls_read_tallies when a history was cut at the flight cap). */
+ * cls_run / cls_read_tallies when a history was cut at the flight cap, see
+ * cls_read_tallies). */
 cls_status cls_run(cls_problem *p, uint64_t histories, uint64_t seed);
 cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed);
 
@@ -158,11 +159,11 @@ typedef struct {
  * each, may be NULL) receive the bin-averaged scalar flux per history and its
  * batch-means one-sigma error; nbins must equal the problem's mesh size.
  * The event counts (flights, collisions, scatters, crossings, reflections) are
- * summed per work chunk in 32 bits before they reach these 64-bit totals: a
- * chunk must hold fewer than 2^32 events of each kind, i.e. max_chunk times the
- * mean flights per history below 4.29e9 (with the default max_chunk of 16384,
- * histories of up to ~2.6e5 flights on average). T, R, A and the flux do not
- * depend on it.
+ * summed per work chunk in 32 bits before they reach these 64-bit totals, so a
+ * history is cut (counted in `capped`, CLS_ERR_EVENT_CAP) after
+ * min(10^8, floor((2^32 - 1) / histories per chunk)) flights: 2.6e5 flights
+ * with the default max_chunk of 16384, 65535 with chunks of 65536 histories
+ * (lower max_chunk with cls_set_launch_config for longer histories).
  * Errors: CLS_ERR_STATE (no completed run), CLS_ERR_NOT_READY, CLS_ERR_INVALID_ARG,
  * CLS_ERR_EVENT_CAP (results are still written). */
 cls_status cls_read_tallies(const cls_problem *p, cls_tallies *out, double *flux,
@@ -252,7 +253,12 @@ cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories,
  *                        ("round") when that much work is queued (0: 3e7); it
  *                        also bounds a request's chunk size (about
  *                        round_histories / resident waves, see below);
- *   max_inflight_rounds  launches queued on the GPU at once (0: 2; at most 8).
+ *   max_inflight_rounds  launches queued on the GPU at once (0: 2; at most 8);
+ *   record_path          0: the tracking kernel that completes a request writes
+ *                        its result record straight into the problem's pinned
+ *                        host record (when the device can address it);
+ *                        1: a finalize kernel and a copy follow the request's
+ *                        last round (the cls_run path). Both give the same record.
  * A worker thread admits requests, runs rounds of one persistent launch over
  * the next chunks of every admitted request of one kernel variant, and copies
  * each request's results back when its last chunk is done. A round holds at
@@ -268,6 +274,7 @@ typedef struct {
     size_t hbm_budget_bytes;
     uint64_t round_histories;
     int max_inflight_rounds;
+    int record_path;
 } cls_server_config;
 typedef struct {
     double submit_s, admit_s, done_s;   /* seconds since server creation (-1: not yet) */

@@ -85,7 +85,7 @@ class cls_launch_config(ctypes.Structure):
 
 class cls_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("round_histories", ctypes.c_uint64),
-                ("max_inflight_rounds", ctypes.c_int)]
+                ("max_inflight_rounds", ctypes.c_int), ("record_path", ctypes.c_int)]
 
 
 class cls_request_info(ctypes.Structure):
@@ -302,8 +302,9 @@ def cls_batch_destroy(b: int) -> None:
 
 
 # ---- serving -----------------------------------------------------------------
-def cls_server_create(hbm_budget_bytes: int = 0, round_histories: int = 0, max_inflight_rounds: int = 0) -> int:
-    cfg = cls_server_config(int(hbm_budget_bytes), int(round_histories), int(max_inflight_rounds))
+def cls_server_create(hbm_budget_bytes: int = 0, round_histories: int = 0, max_inflight_rounds: int = 0,
+                      record_path: int = 0) -> int:
+    cfg = cls_server_config(int(hbm_budget_bytes), int(round_histories), int(max_inflight_rounds), int(record_path))
     h = _P()
     _check(_lib.cls_server_create(ctypes.byref(cfg), ctypes.byref(h)), "cls_server_create")
     return h.value

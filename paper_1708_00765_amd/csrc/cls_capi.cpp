@@ -60,7 +60,6 @@ LaunchShape g_shape = {0, 0, 0, 0};
 constexpr int kDefaultWavesPerBlock = 0;   // 0: chosen per kernel (most resident waves)
 constexpr int kDefaultBlocksPerCu = 0;     // 0: as many as fit (occupancy query)
 constexpr int kDefaultMaxChunk = 16384;
-constexpr uint64_t kDefaultMaxSteps = 100000000ull;
 constexpr size_t kLdsLimit = 65536;
 constexpr int kDefaultRefillMin = 4;
 }  // namespace
@@ -225,7 +224,7 @@ void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, u
     out->chunk = chunk;
     out->chunk_base = 0;
     out->trace_n = trace_n;
-    out->max_steps = kDefaultMaxSteps;
+    out->max_steps = sched::flight_cap(chunk);
     out->nbins = p->nbins;
     out->counters = p->d_counters;
     out->sums = p->d_sums;

@@ -92,8 +92,8 @@ struct TrackArgs {
 };
 
 // LDS per wave beyond its one or two tally buffers: score sums of two slots
-// (4 doubles) and kSlotCounters 32-bit counters per slot (12 doubles).
-constexpr int kSlotCounters = 12;
+// (4 doubles) and kSlotCounters 32-bit counters per slot (8 doubles).
+constexpr int kSlotCounters = 8;
 // ... then the per-material flight parameters of the problem each slot holds:
 // 2 slots x 2 materials x 4 values, room for FP64 values.
 constexpr int kMatTableDoubles = 16;

@@ -18,6 +18,19 @@ namespace sched {
 // least, when its history count allows.
 constexpr uint64_t kMinErrorBatches = 256;
 
+// Flights after which a history is cut (and the run reports it), at most.
+constexpr uint64_t kMaxFlightsPerHistory = 100000000;
+
+// Flight cap of the histories of a problem cut into chunks of `chunk`
+// histories: the kernels sum a chunk's event counts in 32-bit counters, so a
+// chunk may hold at most 2^32 - 1 flights. The cap is the smaller of
+// kMaxFlightsPerHistory and floor((2^32 - 1) / chunk): 65535 flights per
+// history at the largest chunk of 65536 histories, 2.6e5 at the default 16384.
+inline uint64_t flight_cap(uint64_t chunk)
+{
+    return std::min<uint64_t>(kMaxFlightsPerHistory, 0xFFFFFFFFull / std::max<uint64_t>(chunk, 1));
+}
+
 // Chunk of a problem of n histories that runs alone on a grid of waves_total
 // waves: about four chunks per wave (at least 256 histories each), but never
 // fewer chunks than waves while chunks of 64 histories allow it (then

@@ -156,7 +156,9 @@ cls_status prepare(cls_server *s, Request *r)
     // pinned host record when the device can address it; else a finalize
     // kernel and a copy follow the request's last round
     void *dptr = nullptr;
-    r->host_record = hipHostGetDevicePointer(&dptr, p->h_record, 0) == hipSuccess ? (uint64_t *)dptr : nullptr;
+    r->host_record = s->cfg.record_path == 0 && hipHostGetDevicePointer(&dptr, p->h_record, 0) == hipSuccess
+                          ? (uint64_t *)dptr
+                          : nullptr;
     r->prepared = true;
     return CLS_OK;
 }
@@ -439,6 +441,10 @@ cls_status cls_server_create(const cls_server_config *cfg, cls_server **out)
         s->cfg.hbm_budget_bytes = free_b / 10 * 8;
     }
     if (s->cfg.round_histories == 0) s->cfg.round_histories = 30000000ull;
+    if (s->cfg.record_path != 0 && s->cfg.record_path != 1) {
+        delete s;
+        return fail(CLS_ERR_INVALID_ARG, "record_path must be 0 or 1");
+    }
     if (s->cfg.max_inflight_rounds <= 0) s->cfg.max_inflight_rounds = 2;
     s->cfg.max_inflight_rounds = std::min(s->cfg.max_inflight_rounds, 8);
     s->device = di.id;

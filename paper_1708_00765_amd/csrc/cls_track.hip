@@ -124,8 +124,12 @@ __device__ __forceinline__ uint64_t fnv_event(uint64_t h, int ev, int m, int bin
 // ---------------------------------------------------------------------------
 // per-slot bookkeeping (wave-uniform values)
 // ---------------------------------------------------------------------------
-enum SlotCtr : int { S_T = 0, S_R, S_A, S_CAP, S_FLIGHTS, S_COLL, S_SCAT, S_INT, S_LAT, S_NCTR };
-static_assert(S_NCTR <= kSlotCounters, "slot counters do not fit their LDS area");
+// Counters of a chunk slot: the first S_STORED are 64-bit LDS counters that the
+// lanes add their sums to; collisions and lateral reflections are derived at the
+// flush (a collision is a scatter or an absorption; a flight ends in a leak, an
+// absorption, a scatter, an interface crossing or a lateral mirror).
+enum SlotCtr : int { S_T = 0, S_R, S_A, S_CAP, S_FLIGHTS, S_SCAT, S_INT, S_STORED, S_COLL = S_STORED, S_LAT, S_NCTR };
+static_assert(S_STORED <= kSlotCounters, "slot counters do not fit their LDS area");
 static_assert(EV_LEAK_XHI - EV_LEAK_XHI == S_T && EV_LEAK_XHI - EV_LEAK_XLO == S_R &&
                   EV_LEAK_XHI - EV_ABSORB == S_A,
               "outcome counters follow the leak and absorption event codes");
@@ -178,8 +182,9 @@ __device__ __forceinline__ Prm<R> load_prm(ConstProblem &P)
 // between the two materials.
 template <typename R>
 struct alignas(16) MatRow {
-    R ds, dl, isig;
+    R ds, dl;
     uint32_t cthr;
+    R isig;
 };
 static_assert(sizeof(MatRow<float>) == 16 && sizeof(MatRow<double>) == 32, "material rows of 16 / 32 bytes");
 
@@ -221,10 +226,9 @@ struct Lane {
     uint64_t h;
     uint64_t hash;
     uint32_t step;
-    uint32_t n_int, n_scat, n_lat;
+    uint32_t n_int, n_scat, n_fl;   // interface crossings, scatters, flights (of finished histories)
     uint32_t n_t, n_r, n_a, n_cap;
-    int m, slot, pid, kcur;  // material, chunk slot, problem, bin of x
-    int tb;                  // offset of the slot's LDS tally buffer (doubles)
+    int m, slot, kcur;       // material, chunk slot (its problem and LDS buffer), bin of x
     bool alive;
 };
 
@@ -384,15 +388,18 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
             if (FP32) {
                 // overlaps from the in-bin positions: (1 - f) of the lower
                 // end's bin and f of the upper end's, times the bin width
-                // along the track
+                // along the track. The differences are taken in FP64, where
+                // they are exact for FP32 operands, so the four adds of a
+                // flight cancel exactly beyond its last bin (FP32 differences
+                // left a rounding residue in every bin past the track)
                 const R dxw = P.dxr * MM::abs_(L.iux);
-                const R pa = one ? s : ((R)1 - (up ? fa : L.fx)) * dxw;
-                const R pb = one ? (R)0 : (up ? L.fx : fa) * dxw;
-                const R full = one ? (R)0 : dxw;
-                lds_add(tal + ka, (double)pa);
-                lds_add(tal + ka + 1, (double)(full - pa));
-                lds_add(tal + kb, (double)(pb - full));
-                lds_add(tal + kb + 1, -(double)pb);
+                const double pa = (double)(one ? s : ((R)1 - (up ? fa : L.fx)) * dxw);
+                const double pb = one ? 0.0 : (double)((up ? L.fx : fa) * dxw);
+                const double full = one ? 0.0 : (double)dxw;
+                lds_add(tal + ka, pa);
+                lds_add(tal + ka + 1, full - pa);
+                lds_add(tal + kb, pb - full);
+                lds_add(tal + kb + 1, -pb);
             } else {
                 const double lo = up ? xa : L.x;
                 const double hi = up ? L.x : xa;
@@ -457,7 +464,6 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         }
         L.n_int += (uint32_t)intf;
         L.n_scat += (uint32_t)scat;
-        if (AXES >= 2) L.n_lat += (uint32_t)(refl_y || refl_z);
         if (TRACE) L.hash = fnv_event(L.hash, ev, mf, P.trace_bins ? L.kcur : 0);
     }
     // ---- shared direction sampler: polar axis x for the inward cosine-law
@@ -568,6 +574,8 @@ __device__ __forceinline__ void record_into(PR &P, uint64_t *rec, int t, int nt)
 
 // Move a lane's sums to the LDS counters of its slot (a lane that finished no
 // history there holds none) and clear them.
+// The counters are 32-bit: the host caps a history's flights at
+// (2^32 - 1) / (histories per chunk), so no sum over a chunk can wrap.
 template <typename R>
 __device__ __forceinline__ void lane_to_slot(Lane<R> &L, double *wsum, uint32_t *wctr)
 {
@@ -580,14 +588,14 @@ __device__ __forceinline__ void lane_to_slot(Lane<R> &L, double *wsum, uint32_t 
         atomicAdd(c + S_R, L.n_r);
         atomicAdd(c + S_A, L.n_a);
         atomicAdd(c + S_CAP, L.n_cap);
+        atomicAdd(c + S_FLIGHTS, L.n_fl);
         atomicAdd(c + S_SCAT, L.n_scat);
         atomicAdd(c + S_INT, L.n_int);
-        atomicAdd(c + S_LAT, L.n_lat);
     }
     L.ssum = 0.0;
     L.ssq = 0.0;
     L.n_t = L.n_r = L.n_a = L.n_cap = 0u;
-    L.n_int = L.n_scat = L.n_lat = 0u;
+    L.n_int = L.n_scat = L.n_fl = 0u;
 }
 
 // Move a finished chunk's tallies from its LDS slot to HBM: the flux bins
@@ -603,6 +611,22 @@ __device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, dou
     double *Sk = P.sums + 2;
     double *Qk = P.sums + 2 + KK;
     const double inv_n = 1.0 / (double)S.cnt;
+    // Track length: the four entries of each flight sum to zero, so from the
+    // last nonzero entry of the difference buffer on the exact running sum is
+    // zero (no track reached those bins); the accumulated entries would leave
+    // a rounding residue of ~1e-17 there, so those bins are not added at all.
+    int kend = KK;
+    if (EST == EST_TRACK) {
+        kend = 0;
+        for (int base = (KK / 64) * 64; base >= 0; base -= 64) {
+            const int k = base + lane;
+            const uint64_t nz = ballot(k <= KK && b[k] != 0.0);
+            if (nz != 0) {
+                kend = base + 63 - __builtin_clzll(nz);
+                break;
+            }
+        }
+    }
     double carry = 0.0;
     for (int base = 0; base <= KK; base += 64) {
         const int k = base + lane;
@@ -611,7 +635,7 @@ __device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, dou
             v = wave_inclusive_scan(v, lane) + carry;
             carry = __shfl(v, 63, 64);
         }
-        if (k < KK && v != 0.0) {
+        if (k < kend && v != 0.0) {
             atomicAdd(Sk + k, v);
             atomicAdd(Qk + k, v * v * inv_n);
         }
@@ -619,17 +643,18 @@ __device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, dou
     }
     const double st = ssum[0];
     const double st2 = ssum[1];
-    // one counter per lane: lanes 0..S_NCTR-1 move them to HBM. Flights and
-    // collisions are derived: a flight ends in a leak (T, R), an absorption, a
-    // scatter, an interface crossing or a lateral mirror (a capped history's
-    // refused step is no flight); a collision is a scatter or an absorption.
-    uint64_t cv = lane < S_NCTR ? c[lane] : 0u;
-    const uint64_t n_t = c[S_T], n_r = c[S_R], n_a = c[S_A], n_sc = c[S_SCAT], n_in = c[S_INT], n_la = c[S_LAT];
-    if (lane == S_FLIGHTS) cv = n_t + n_r + n_a + n_sc + n_in + n_la;
+    // one counter per lane: lanes 0..S_NCTR-1 move them to HBM. Collisions and
+    // lateral mirror reflections are derived: a collision is a scatter or an
+    // absorption; a flight ends in a leak (T, R), an absorption, a scatter, an
+    // interface crossing or a lateral mirror (a capped history's refused step
+    // is no flight).
+    uint64_t cv = lane < S_STORED ? c[lane] : 0u;
+    const uint64_t n_t = c[S_T], n_r = c[S_R], n_a = c[S_A], n_sc = c[S_SCAT], n_in = c[S_INT], n_fl = c[S_FLIGHTS];
     if (lane == S_COLL) cv = n_sc + n_a;
-    if (lane < S_NCTR) c[lane] = 0u;
+    if (lane == S_LAT) cv = n_fl - (n_t + n_r + n_a + n_sc + n_in);
+    if (lane < S_STORED) c[lane] = 0u;
     const int slot_ctr_to_global[S_NCTR] = {C_TRANSMITTED, C_REFLECTED, C_ABSORBED, C_CAPPED, C_FLIGHTS,
-                                            C_COLLISIONS, C_SCATTERS, C_INTERFACES, C_LATERAL};
+                                            C_SCATTERS, C_INTERFACES, C_COLLISIONS, C_LATERAL};
     unsigned long long *Cg = (unsigned long long *)P.counters;
     if (lane < S_NCTR && cv != 0u) atomicAdd(Cg + slot_ctr_to_global[lane], (unsigned long long)cv);
     if (lane == 0) {
@@ -687,9 +712,9 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     L.x = 0.0; L.dy = L.dz = L.ux = L.uy = L.uz = 0;
     L.iux = L.aiuy = L.aiuz = 0; L.ig = 1; L.fx = 0;
     L.tscore = 0.0; L.ssum = 0.0; L.ssq = 0.0; L.h = 0; L.hash = 0; L.step = 0;
-    L.n_int = L.n_scat = L.n_lat = 0;
+    L.n_int = L.n_scat = L.n_fl = 0;
     L.n_t = L.n_r = L.n_a = L.n_cap = 0;
-    L.m = 0; L.slot = 0; L.pid = 0; L.kcur = 0; L.tb = 0; L.alive = false;
+    L.m = 0; L.slot = 0; L.kcur = 0; L.alive = false;
 
     for (;;) {
         // ---------------- hand out histories to idle lanes ----------------
@@ -751,8 +776,6 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                     // sums of the lane's histories in the other slot go there first
                     if (L.slot != cp) lane_to_slot(L, wsum, wctr);
                     L.slot = cp;
-                    L.tb = cp * KP;
-                    L.pid = C.pid;
                     L.h = C.h0 + C.next + r;
                     L.step = 0u;
                     L.tscore = 0.0;
@@ -769,18 +792,21 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
         if (dead == ~0ull && queue_empty && !C.open && !O.open) break;
 
         // ---------------- one event step per live lane -----------------------
-        // A wave holds lanes of at most two problems (one per slot); each pass
-        // steps the lanes of one problem with its parameters in scalars.
+        // A wave holds lanes of at most two problems (one per slot: a live lane
+        // is in an open slot); each pass steps the lanes of one problem with
+        // its parameters in scalars, both slots at once when they hold the
+        // same problem.
         int ev = EV_NONE;
         uint64_t todo = ballot(L.alive);
+        const bool same = C.open && O.open && C.pid == O.pid;
         while (todo != 0) {
-            const int first = __builtin_ctzll(todo);
-            const int pidc = __builtin_amdgcn_readlane(L.pid, first);
-            const bool mine = L.alive && L.pid == pidc && ((todo >> lane) & 1ull);
+            const int sc = __builtin_amdgcn_readlane(L.slot, __builtin_ctzll(todo));
+            const int pidc = sc == cp ? C.pid : O.pid;
+            const bool mine = L.alive && ((todo >> lane) & 1ull) && (same || L.slot == sc);
             if (mine) {
                 ConstProblem *cprob = (ConstProblem *)A.probs;
-                const Prm<R> P = load_prm<R>(cprob[__builtin_amdgcn_readfirstlane(pidc)]);
-                ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + L.tb, wmat + 2 * L.slot);
+                const Prm<R> P = load_prm<R>(cprob[pidc]);
+                ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + (L.slot ? KP : 0), wmat + 2 * L.slot);
             }
             todo &= ~ballot(mine);
         }
@@ -800,8 +826,10 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                 L.n_r += ev == EV_LEAK_XLO ? 1u : 0u;
                 L.n_a += ev == EV_ABSORB ? 1u : 0u;
                 L.n_cap += ev == EV_CAP ? 1u : 0u;
+                // steps = source + flights (+ the refused step of a capped history)
+                L.n_fl += L.step - 1u - (ev == EV_CAP ? 1u : 0u);
                 if (TRACE) {
-                    const DevProblem &P = A.probs[L.pid];
+                    const DevProblem &P = A.probs[L.slot == cp ? C.pid : O.pid];
                     if (L.h < P.trace_n) {
                         // steps = source + flights (+ the refused step of a capped history)
                         P.trace_hash[L.h] = L.hash;

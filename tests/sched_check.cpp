@@ -142,6 +142,18 @@ int main()
                   "items %llu f %g -> %llu", (unsigned long long)items, f, (unsigned long long)k);
         ++cases;
     }
+    // flight cap: a chunk's flights fit a 32-bit counter, and the cap is as
+    // large as that allows (never above the global cap)
+    for (int t = 0; t < 100000; ++t) {
+        const uint64_t c = t < 70000 ? (uint64_t)(t + 1) : log_uniform(1, 4.0e9);
+        const uint64_t cap = flight_cap(c);
+        CHECK(cap >= 1 && cap <= kMaxFlightsPerHistory, "chunk=%llu cap=%llu", (unsigned long long)c,
+              (unsigned long long)cap);
+        CHECK(c * cap <= 0xFFFFFFFFull, "chunk=%llu cap=%llu", (unsigned long long)c, (unsigned long long)cap);
+        CHECK(cap == kMaxFlightsPerHistory || c * (cap + 1) > 0xFFFFFFFFull, "chunk=%llu cap=%llu",
+              (unsigned long long)c, (unsigned long long)cap);
+        ++cases;
+    }
     printf("%s %ld cases, %d failures\n", failures ? "FAILED" : "OK", cases, failures);
     return failures ? 1 : 0;
 }

@@ -21,12 +21,13 @@ def test_more_than_one_gpu_is_refused():
 
 @pytest.mark.gpu
 def test_bench_line_on_a_small_run():
-    """A reduced run (1e6 histories per set, FP64 leg, 1 s of oracle) prints the
+    """A reduced run of the stress3d sets (1e6 histories per set, FP64 leg, 1 s of
+    oracle) prints the
     JSON line with every field the benchmark reports; the measured traffic is
     only reported for the full workload."""
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "1", "--warmup", "0",
            "--histories", "1000000", "--fp64-steps", "1", "--cpu-seconds", "1", "--serve-seconds", "0",
-           "--saturate-seconds", "0", "--ext2d-steps", "0", "--quenched-histories", "0"]
+           "--saturate-seconds", "0", "--ext2d-steps", "0", "--quenched-histories", "0", "--cube3d-steps", "0"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=300, cwd=ROOT)
     print(r.stderr[-2000:])
     assert r.returncode == 0, r.stderr[-2000:]
@@ -48,3 +49,7 @@ def test_bench_line_on_a_small_run():
     assert cpu["kind"] == "oracle" and cpu["value"] > 0 and cpu["cores"] >= 1 and cpu["unit"] == "histories/s"
     assert isinstance(cpu["sample"], str) and cpu["sample"]
     assert j["fp64_plain"]["value"] > 0
+    acc = j["fp32_vs_fp64_same_streams"]
+    assert acc["bins_compared"] == 32 * 1000 and set(acc["violations"]) == {"scalars", "profiles", "bins"}
+    orc = j["fp32_vs_oracle"]
+    assert orc["bins"] > 0 and orc["oracle_histories_per_set"] > 0
