@@ -310,6 +310,38 @@ cls_status cls_server_get_stats(cls_server *s, cls_server_stats *out);
 void cls_server_destroy(cls_server *s);
 
 /* ---------------------------------------------------------------------- */
+/* Allocation-free run                                                    */
+/* ---------------------------------------------------------------------- */
+/* For callers that cannot allocate device or pinned memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Runs `histories` histories of p with stream key `seed` exactly as
+ * cls_run_async would (same launch shape, chunks and kernels; integer tallies
+ * bitwise equal, FP64 sums up to the order of additions), but allocates
+ * nothing: the run's device workspace is a static 48 KB array that the library
+ * holds on each device it runs on until the process ends, and nothing is
+ * copied to the host.
+ *   p            a problem from cls_create_problem (only read; CLS_F_TRACE is
+ *                rejected; nbins <= CLS_MAX_BINS).
+ *   hip_stream   hipStream_t the work is enqueued on (NULL = default stream);
+ *                the call returns at once, the caller synchronizes.
+ *   d_record     caller-owned device memory, 8-byte aligned, of at least
+ *                record_bytes = (24 + 2 nbins) x 8 bytes, receiving the result
+ *                record: 16 uint64 counters (histories, transmitted, reflected,
+ *                absorbed, capped, flights, collisions, scatters, interface
+ *                crossings, lateral reflections, batches, then 5 reserved), 8
+ *                doubles (T, R, A, sigma_T, sigma_R, sigma_A, total flux, its
+ *                sigma), then flux[nbins] and flux_sigma[nbins] as in
+ *                cls_read_tallies.
+ * Every call on a device reuses that device's array: calls that overlap on one
+ * device (two streams, two threads) race and give wrong results; calls ordered
+ * by the caller are independent.
+ * Errors: CLS_ERR_INVALID_ARG (NULL arguments, histories == 0, trace problem,
+ * nbins above CLS_MAX_BINS, record buffer too small or misaligned),
+ * CLS_ERR_NO_DEVICE, CLS_ERR_DEVICE. */
+cls_status cls_run_static(const cls_problem *p, uint64_t histories, uint64_t seed, void *hip_stream,
+                          void *d_record, size_t record_bytes);
+
+/* ---------------------------------------------------------------------- */
 /* Quenched-disorder reference solutions, d = 1 (Section 3)               */
 /* ---------------------------------------------------------------------- */
 /* Reference solutions average each observable over realizations of the

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcls_hip.so")
 
-SOURCES = ["cls_track.hip", "cls_quenched.hip", "cls_capi.cpp", "cls_graph.cpp", "cls_autotune.cpp", "cls_server.cpp",
+SOURCES = ["cls_track.hip", "cls_quenched.hip", "cls_static.hip", "cls_capi.cpp", "cls_graph.cpp", "cls_autotune.cpp", "cls_server.cpp",
            "cls_quenched_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

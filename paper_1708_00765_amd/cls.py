@@ -54,7 +54,7 @@ EXPORTED = (
     "cls_set_launch_config", "cls_get_launch_config", "cls_autotune",
     "cls_server_create", "cls_server_submit", "cls_server_poll", "cls_server_wait",
     "cls_server_request_info", "cls_server_release", "cls_server_get_stats", "cls_server_destroy",
-    "cls_run_quenched", "cls_read_quenched",
+    "cls_run_quenched", "cls_read_quenched", "cls_run_static",
     "cls_status_string", "cls_last_error", "cls_version",
 )
 
@@ -143,6 +143,7 @@ _sig("cls_server_destroy", None, _P)
 _sig("cls_set_launch_config", ctypes.c_int, ctypes.POINTER(cls_launch_config))
 _sig("cls_get_launch_config", ctypes.c_int, ctypes.POINTER(cls_launch_config))
 _sig("cls_run_quenched", ctypes.c_int, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64)
+_sig("cls_run_static", ctypes.c_int, _P, ctypes.c_uint64, ctypes.c_uint64, _P, _P, ctypes.c_size_t)
 _sig("cls_read_quenched", ctypes.c_int, _P, ctypes.POINTER(cls_quenched_tallies), _P, _P, ctypes.c_int)
 _sig("cls_status_string", ctypes.c_char_p, ctypes.c_int)
 _sig("cls_last_error", ctypes.c_char_p)
@@ -351,6 +352,33 @@ def cls_server_get_stats(s: int) -> dict:
 
 def cls_server_destroy(s: int) -> None:
     _lib.cls_server_destroy(s)
+
+
+def cls_run_static(p: int, histories: int, seed: int, stream: int | None, d_record: int, record_bytes: int) -> None:
+    """Allocation-free run (enqueued on `stream`; the caller synchronizes). `d_record`
+    is caller-owned device memory of at least record_bytes(nbins) bytes."""
+    _check(_lib.cls_run_static(p, int(histories), int(seed) & (2**64 - 1), stream or None, int(d_record),
+                               int(record_bytes)), "cls_run_static")
+
+
+RECORD_COUNTERS = ("histories", "transmitted", "reflected", "absorbed", "capped", "flights", "collisions",
+                   "scatters", "interface_crossings", "lateral_reflections", "batches")
+RECORD_DOUBLES = ("T", "R", "A", "sigma_T", "sigma_R", "sigma_A", "total_flux", "sigma_total_flux")
+
+
+def record_bytes(nbins: int) -> int:
+    """Size of the result record of cls_run_static: 16 counters, 8 doubles, 2 x nbins doubles."""
+    return (24 + 2 * int(nbins)) * 8
+
+
+def decode_record(words, nbins: int):
+    """Split a result record (the 8-byte words as a numpy uint64 array) into a dict of
+    the counters and scalars, flux[nbins] and flux_sigma[nbins]."""
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    d = w[16:].view(np.float64)
+    out = {k: int(w[i]) for i, k in enumerate(RECORD_COUNTERS)}
+    out.update({k: float(d[i]) for i, k in enumerate(RECORD_DOUBLES)})
+    return out, d[8:8 + nbins].copy(), d[8 + nbins:8 + 2 * nbins].copy()
 
 
 def cls_run_quenched(p: int, realizations: int, histories: int, seed: int) -> None:
