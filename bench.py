@@ -382,6 +382,39 @@ def run_ext2d_comparison(cls, torch, stream, steps):
             "fp32_vs_fp64_same_streams": fp32_acceptance(full32, full64)}
 
 
+def _server_line(cls, srv, label):
+    st = cls.cls_server_get_stats(srv)
+    return (f"{label}: submitted {st['submitted']}, completed {st['completed']}, failed {st['failed']}, "
+            f"pending {st['pending']}, active {st['active']}, rounds {st['rounds']}")
+
+
+def _wait_all(cls, srv, tickets, label, limit_s=60.0):
+    """Wait for every ticket, logging progress every 10 s; a request that is not
+    done `limit_s` after the previous completion ends the leg with an error."""
+    last = time.perf_counter()
+    for tk in tickets:
+        while not cls.cls_server_wait(srv, tk, 10.0):
+            log(_server_line(cls, srv, label + " (waiting)"))
+            if time.perf_counter() - last > limit_s:
+                raise RuntimeError(f"{label}: request {tk} not done {limit_s:.0f} s after the previous one; "
+                                   + _server_line(cls, srv, "server"))
+        last = time.perf_counter()
+
+
+def _latency_stages(infos):
+    """p50 / p99 in ms of each stage of a served request: submission to its first
+    chunk published, to the completion signal seen by the worker, to the finalize
+    launch, to the result on the host."""
+    import numpy as np
+    keys = ("submit_s", "publish_s", "signal_s", "finalize_s", "done_s")
+    out = {}
+    for a, b in zip(keys, keys[1:]):
+        d = np.array([i[b] - i[a] for i in infos if i[a] >= 0 and i[b] >= 0]) * 1e3
+        if len(d):
+            out[f"{a[:-2]}_to_{b[:-2]}"] = {"p50": float(np.percentile(d, 50)), "p99": float(np.percentile(d, 99))}
+    return out
+
+
 def run_served(cls, seconds, rate):
     """Submit the served workload's Poisson stream in real time; latency is
     arrival to results on the host, measured by the server's clock."""
@@ -391,23 +424,27 @@ def run_served(cls, seconds, rate):
     srv = cls.cls_server_create()
     live = []
     t0 = time.perf_counter()
+    next_log = 10.0
+    log(f"served: {len(reqs)} requests over {seconds:g} s")
     try:
         for t_arr, s in reqs:
             delay = t0 + t_arr - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
+            if t_arr >= next_log:
+                log(_server_line(cls, srv, f"served at {t_arr:.0f} s"))
+                next_log += 10.0
             p = make_problem(cls, s, fp32=True)
             live.append((cls.cls_server_submit(srv, p, s.histories, s.seed), p, s))
-        infos = []
-        for tk, p, s in live:
-            cls.cls_server_wait(srv, tk, 600.0)
-            infos.append(cls.cls_server_request_info(srv, tk))
+        _wait_all(cls, srv, [tk for tk, _, _ in live], "served")
+        infos = [cls.cls_server_request_info(srv, tk) for tk, _, _ in live]
         stats = cls.cls_server_get_stats(srv)
     finally:
         cls.cls_server_destroy(srv)
         for _, p, _ in live:
             cls.cls_destroy_problem(p)
     lat = np.array([i["done_s"] - i["submit_s"] for i in infos]) * 1e3
+    stages = _latency_stages(infos)
     first = min(i["submit_s"] for i in infos)
     last = max(i["done_s"] for i in infos)
     hist = sum(i["histories"] for i in infos)
@@ -416,7 +453,8 @@ def run_served(cls, seconds, rate):
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "max_ms": float(lat.max()), "histories": hist, "histories_per_s": hist / (last - first),
             "offered_histories_per_s": hist / seconds, "rounds": stats["rounds"],
-            "hbm_peak_bytes": stats["hbm_peak"],
+            "wave_idle_share": stats["wave_idle_share"],
+            "hbm_peak_bytes": stats["hbm_peak"], "latency_stages_ms": stages,
             "workload": "served: d uniform in {1 (rod, collision flux), 2 (ext2d), 3 (cube3d)}, "
                         "histories log-uniform in [1e4, 1e8], 10-1000 bins, FP32 tracking"}
 
@@ -433,8 +471,7 @@ def run_served_saturated(cls, rate, seconds):
     srv = cls.cls_server_create()
     try:
         tickets = [cls.cls_server_submit(srv, p, s.histories, s.seed) for p, s in zip(probs, specs)]
-        for tk in tickets:
-            cls.cls_server_wait(srv, tk, 600.0)
+        _wait_all(cls, srv, tickets, "served at saturation")
         infos = [cls.cls_server_request_info(srv, tk) for tk in tickets]
         stats = cls.cls_server_get_stats(srv)
     finally:
@@ -456,7 +493,7 @@ def run_served_saturated(cls, rate, seconds):
     peak = perf_model.PEAK_SLOTS_PER_S / 1e12
     return {"requests": len(specs), "completed": stats["completed"], "failed": stats["failed"],
             "histories": hist, "flights": flights, "seconds": span, "value": hist / span, "unit": "histories/s",
-            "rounds": stats["rounds"],
+            "rounds": stats["rounds"], "wave_idle_share": stats["wave_idle_share"],
             "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
                          "frac": achieved / peak, "algorithmic_slots": slots},
             "workload": f"served mix (as the Poisson stream), the {len(specs)} requests of {seconds:g} s at "
@@ -648,7 +685,8 @@ def main() -> int:
     if args.serve_seconds > 0:
         served = run_served(cls, args.serve_seconds, args.serve_rate)
         log(f"served: {served['completed']} requests, p50 {served['p50_ms']:.1f} ms, "
-            f"p99 {served['p99_ms']:.1f} ms, {served['histories_per_s']:.4g} hist/s")
+            f"p99 {served['p99_ms']:.1f} ms, {served['histories_per_s']:.4g} hist/s; stages (p50/p99 ms) "
+            + ", ".join(f"{k} {v['p50']:.2f}/{v['p99']:.2f}" for k, v in served["latency_stages_ms"].items()))
     served_sat = None
     if args.saturate_seconds > 0:
         served_sat = run_served_saturated(cls, 600.0, args.saturate_seconds)

@@ -249,26 +249,33 @@ cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories,
  *                        admitted requests (0: 80% of the free device memory);
  *                        a request that does not fit waits in arrival order
  *                        (one is always admitted when nothing else is);
- *   round_histories      smallest size in histories of a batched launch
- *                        ("round") when that much work is queued (0: 3e7); it
- *                        also bounds a request's chunk size (about
- *                        round_histories / resident waves, see below);
- *   max_inflight_rounds  launches queued on the GPU at once (0: 2; at most 8);
- *   record_path          0: the tracking kernel that completes a request writes
- *                        its result record straight into the problem's pinned
- *                        host record (when the device can address it);
- *                        1: a finalize kernel and a copy follow the request's
- *                        last round (the cls_run path). Both give the same record.
- * A worker thread admits requests, runs rounds of one persistent launch over
- * the next chunks of every admitted request of one kernel variant, and copies
- * each request's results back when its last chunk is done. A round holds at
- * least round_histories and at least six of its largest chunks per resident
- * wave (a round lasts at least as long as one wave takes for its largest
- * chunk), shared equally between its requests: one with less left finishes in
- * that round, the others get equal shares of the rest (at least one chunk).
- * Requests that arrive while others run join the next round. Each result is the one
- * cls_run would give for the same problem, histories and seed (integer
- * tallies bitwise, FP64 sums up to atomic ordering). */
+ *   round_histories      bounds a request's chunk size (work item and error
+ *                        batch) to about round_histories / resident waves
+ *                        (0: 3e7), while a request keeps at least 256 chunks
+ *                        when its history count allows;
+ *   max_inflight_rounds  ignored (a server keeps at most two launches, one
+ *                        open and one draining);
+ *   record_path          0: the finalize kernel writes each request's result
+ *                        record straight into the problem's pinned host record
+ *                        (when the device can address it); 1: into device memory,
+ *                        then a copy. Both give the same record.
+ * A worker thread admits requests and keeps one persistent tracking launch (a
+ * "round") open at a time: the served kernel handles every geometry,
+ * estimator and source of one precision, and takes its work from a queue in
+ * pinned host memory that the worker feeds while it runs (small requests whole
+ * as they arrive, large ones metered chunk by chunk), so a request that
+ * arrives while the round still has work to publish joins it at once. The
+ * round is closed (it drains; a later request starts a new one) once it has
+ * nothing left to publish, and after a 10 ms slice when a request it cannot
+ * take waits (the other precision, or a mesh finer than its LDS buffers, which
+ * hold at least 1024 bins). The wave that flushes a request's last chunk
+ * signals the worker, which launches a finalize kernel for it while the round
+ * goes on. Each result is the one cls_run would give for the same problem,
+ * histories and seed (integer tallies bitwise, FP64 sums up to atomic
+ * ordering). A device-side protocol error (a chunk the kernel refuses, a wave
+ * that waited too long for its work, or a request whose chunks all ran without
+ * a completion signal) fails every unfinished request and stops the server
+ * (worker_status is set; later submissions fail with CLS_ERR_STATE). */
 typedef struct cls_server cls_server;
 typedef struct {
     size_t hbm_budget_bytes;
@@ -280,21 +287,28 @@ typedef struct {
     double submit_s, admit_s, done_s;   /* seconds since server creation (-1: not yet) */
     uint64_t histories;
     uint32_t rounds;                     /* launches that carried the request's chunks */
+    /* stages (seconds since server creation, -1: not reached): first chunk
+     * published to a round, completion signal seen by the worker, finalize
+     * launched */
+    double publish_s, signal_s, finalize_s;
 } cls_request_info;
 typedef struct {
     uint64_t submitted, completed, failed, pending, active, rounds, histories_completed;
     size_t hbm_in_use, hbm_peak, hbm_budget;
     int worker_status;                   /* last worker error (cls_status), 0 if none */
+    double wave_idle_share;              /* of the time the rounds' waves were alive, the
+                                            share they had no history to step and waited
+                                            for work (rounds retired so far) */
 } cls_server_stats;
 
 /* cfg may be NULL (all defaults). Errors: CLS_ERR_NO_DEVICE, CLS_ERR_DEVICE. */
 cls_status cls_server_create(const cls_server_config *cfg, cls_server **out);
 /* Queue a run of p (not CLS_F_TRACE; one request per problem at a time; the
- * problem must not be used otherwise until the request is done). When the
- * calling thread's current device is the server's, this call also prepares
- * the request on the device (allocates the problem's memory, writes its
- * record, resets its tallies; CLS_ERR_OUT_OF_MEMORY, CLS_ERR_DEVICE), so that
- * the worker does not have to. */
+ * problem must not be used otherwise until the request is done). Host work
+ * only (chunking, a done word, the problem's pinned result record); the
+ * request's tallies are placed in the server's device pool when it is
+ * admitted. Errors: CLS_ERR_INVALID_ARG, CLS_ERR_STATE (problem already in
+ * flight, server stopping or stopped), CLS_ERR_OUT_OF_MEMORY. */
 cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, uint64_t seed,
                              uint64_t *ticket);
 /* CLS_OK when done (read results with cls_read_tallies on the problem),

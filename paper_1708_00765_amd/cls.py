@@ -90,14 +90,15 @@ class cls_server_config(ctypes.Structure):
 
 class cls_request_info(ctypes.Structure):
     _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double),
-                ("histories", ctypes.c_uint64), ("rounds", ctypes.c_uint32)]
+                ("histories", ctypes.c_uint64), ("rounds", ctypes.c_uint32), ("publish_s", ctypes.c_double),
+                ("signal_s", ctypes.c_double), ("finalize_s", ctypes.c_double)]
 
 
 class cls_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "failed", "pending", "active",
                                                "rounds", "histories_completed")] + \
         [(n, ctypes.c_size_t) for n in ("hbm_in_use", "hbm_peak", "hbm_budget")] + \
-        [("worker_status", ctypes.c_int)]
+        [("worker_status", ctypes.c_int), ("wave_idle_share", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p

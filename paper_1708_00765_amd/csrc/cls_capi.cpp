@@ -226,6 +226,8 @@ void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, u
     out->trace_n = trace_n;
     out->max_steps = sched::flight_cap(chunk);
     out->nbins = p->nbins;
+    out->kind = problem_kind(p->geom, p->est, p->src);
+    out->kind_pad = 0;
     out->counters = p->d_counters;
     out->sums = p->d_sums;
     out->record = p->d_record;
@@ -240,7 +242,8 @@ uint64_t trace_count(const cls_problem *p, uint64_t histories)
 
 bool same_variant(const Variant &a, const Variant &b)
 {
-    return a.geom == b.geom && a.est == b.est && a.src == b.src && a.fp32 == b.fp32 && a.trace == b.trace;
+    return a.geom == b.geom && a.est == b.est && a.src == b.src && a.fp32 == b.fp32 && a.trace == b.trace &&
+           a.served == b.served;
 }
 
 cls_status check_problem_set(cls_problem *const *problems, int n, const uint64_t *histories,
@@ -287,8 +290,8 @@ Variant variant_of(const cls_problem *p)
 static hipError_t occupancy_cached(const Variant &v, int device, int block, size_t lds, int *bpc)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, bool, bool, int, size_t>, int> cache;
-    const auto key = std::make_tuple(device, v.geom, v.est, v.src, v.fp32, v.trace, block, lds);
+    static std::map<std::tuple<int, int, int, int, bool, bool, bool, int, size_t>, int> cache;
+    const auto key = std::make_tuple(device, v.geom, v.est, v.src, v.fp32, v.trace, v.served, block, lds);
     {
         std::lock_guard<std::mutex> lk(mu);
         const auto it = cache.find(key);

@@ -12,6 +12,12 @@ enum Geom : int { GEOM_ROD = 0, GEOM_SLAB = 1, GEOM_EXT2D = 2, GEOM_CUBE3D = 3 }
 enum Est : int { EST_COLLISION = 0, EST_TRACK = 1 };
 enum Src : int { SRC_FACE = 0, SRC_VOLUME = 1 };
 
+// Served rounds run one kernel per precision for every geometry, estimator
+// and source: each problem record carries its kind, and the kernel branches
+// on it per problem (a wave-uniform branch).
+constexpr int GEOM_ANY = -1;
+constexpr int problem_kind(int geom, int est, int src) { return geom | (est << 2) | (src << 3); }
+
 // Trace event codes (same numbering as the documented trace format).
 enum Event : int {
     EV_SOURCE = 0, EV_INTERFACE = 1, EV_SCATTER = 2, EV_ABSORB = 3,
@@ -39,8 +45,11 @@ enum Result : int {
 inline size_t record_words(int nbins) { return (size_t)C_COUNT + R_HEADER + 2 * (size_t)nbins; }
 
 // Per-problem parameters and output pointers, one record per problem of a
-// launch (device memory).
-struct alignas(16) DevProblem {
+// launch (device memory, or pinned host memory for a served round's table).
+// 128-byte aligned and a multiple of 128 bytes, so that no cache line holds
+// parts of two records: the host writes a served round's record while the
+// kernel reads other records of that table.
+struct alignas(128) DevProblem {
     double L, inv_dx, dx;
     double sigma[2], c[2], lam[2];
     double p0;                  // Lambda_0 / (Lambda_0 + Lambda_1)
@@ -67,16 +76,59 @@ struct alignas(16) DevProblem {
     uint64_t max_steps;         // flight cap per history
     int32_t nbins;
     float dxf;                  // FP32 copy of dx
+    int32_t kind;               // problem_kind(geometry, estimator, source)
+    int32_t kind_pad;
     uint64_t *counters;         // C_COUNT u64
     double *sums;               // [0] score sum, [1] score square sum, [2..2+K) S_k, [2+K..2+2K) Q_k
     uint64_t *record;           // finalize output, record_words(K) words
     uint64_t *trace_hash;
     uint32_t *trace_len;
-    // Served requests: the request's total chunk count, and the device address
-    // of its pinned host record. When non-zero, the wave that flushes the last
-    // chunk writes the finalized record there (no finalize kernel or copy).
+    // Served requests (final_chunks != 0): the request's total chunk count;
+    // the wave that flushes its last chunk writes the finalized record into
+    // host_record (device address of pinned host memory) when it is set and
+    // clears the tallies for the next request of that memory, then stores
+    // `tag` into *done_word (pinned) to tell the host the request is complete.
     uint64_t final_chunks;
     uint64_t *host_record;
+    uint64_t *done_word;
+    uint64_t tag;
+};
+static_assert(sizeof(DevProblem) % 128 == 0, "problem records span whole cache lines");
+
+// Work queue of a served round, in pinned host memory that the kernel reads
+// while it runs. An item is (table entry << 32) | chunk index, or
+// kServedLeave. The host writes an entry's record into the round's table
+// (pinned too) before the entry's first item, writes items, and then raises
+// `published`. A wave takes the next item index (a ticket) with one fetch-add
+// on the device-side head and runs the item once `published` covers it; until
+// then it keeps stepping the histories it has and looks again, at growing
+// intervals (counted in loop passes: a waiting wave does not read the clock,
+// whose reads share the scalar memory path with the working waves). Tickets go out in order, so every item before the first
+// kServedLeave is run before any wave receives one. To end a round the host
+// publishes one kServedLeave per wave after the last item: each wave leaves on
+// the first it receives, so every wave leaves and every published item runs.
+// A wave that waits longer than wait_passes for its ticket, or receives an item
+// it refuses (an entry outside the table, a chunk outside its entry's range,
+// an unknown kind of problem), reports it in `error` and leaves: a broken
+// round ends in an error, never in a wave that cannot finish.
+struct ServedFeed {
+    uint64_t published;          // items written (host)
+    uint64_t seen;               // a recent ticket, reported by the waves (every 32nd)
+    uint64_t error;              // kServedErr* of the last failure, 0 if none
+    uint64_t error_item;         // the item (or ticket) concerned
+    uint64_t pad[4];
+};
+
+constexpr uint64_t kServedLeave = ~0ull;
+enum ServedError : uint64_t { kServedErrBadItem = 1, kServedErrWait = 2 };
+
+// Device side of a served round: the ticket counter, and the device
+// wall-clock ticks its waves were alive and, of those, idle (no history to
+// step) while waiting for their ticket to be published.
+struct ServedDev {
+    uint64_t head;
+    unsigned long long alive_ticks, idle_ticks;
+    uint64_t pad[5];
 };
 
 // Everything one tracking launch needs.
@@ -88,7 +140,13 @@ struct TrackArgs {
     int lds_stride;              // doubles per tally buffer (>= max nbins + 1, even)
     int refill_min;              // idle lanes a wave waits for before handing out histories
     int slots;                   // LDS tally buffers per wave: 2, or 1 (fine meshes, large chunks)
-    unsigned long long *exit_count = nullptr;   // served rounds: waves that have left (zeroed before)
+    // served rounds (feed != nullptr): work comes from the feed's queue
+    // instead of item_start; probs is the round's table of entries (device
+    // address of pinned host memory)
+    ServedFeed *feed = nullptr;          // device address of the pinned feed
+    const uint64_t *items = nullptr;     // device address of the pinned item array
+    ServedDev *served = nullptr;         // zeroed before the launch
+    uint64_t wait_passes = 0;            // idle passes (s_sleep 127 each) a wave waits for its ticket at most
 };
 
 // LDS per wave beyond its one or two tally buffers: score sums of two slots
@@ -107,10 +165,12 @@ struct LaunchShape {
     int slots = 2;               // chosen by the launch sizing, not by the caller
 };
 
-// Kernel variants: geometry x estimator x source x precision x trace.
+// Kernel variants: geometry x estimator x source x precision x trace, and
+// whether the launch is a served round (work from a ServedFeed).
 struct Variant {
     int geom, est, src;
     bool fp32, trace;
+    bool served = false;
 };
 
 // Host launchers implemented next to the kernels. They enqueue on `stream`
@@ -120,6 +180,9 @@ hipError_t launch_reset(const DevProblem *d_probs, int nprobs, uint64_t *queue_h
 hipError_t launch_track(const Variant &v, const TrackArgs &args, int grid, int block,
                         size_t lds_bytes, hipStream_t stream);
 hipError_t launch_finalize(const DevProblem *d_probs, int nprobs, hipStream_t stream);
+// Served requests: record into P.record, then clear the tallies (one wave per
+// problem; `probs` may be pinned host memory).
+hipError_t launch_finalize_clear(const DevProblem *probs, int nprobs, hipStream_t stream);
 // Resident workgroups per compute unit of the tracking kernel for a block of
 // `block` threads with `lds_bytes` of dynamic LDS.
 hipError_t track_occupancy(const Variant &v, int block, size_t lds_bytes, int *blocks_per_cu);

@@ -1,17 +1,36 @@
 // Continuous-batching CLS server.
 //
 // Requests (a problem, a history count and a seed) are admitted in arrival
-// order while the summed device footprint of admitted requests stays within
-// the HBM budget; an admitted request's tallies stay resident until it
-// completes. A worker thread issues "rounds": one batched persistent launch of
-// the tracking kernel over the next chunks of every admitted request of one
-// kernel variant (round-robin over variants), of at least round_histories and
-// at least kRoundChunksPerWave of the largest chunks per wave, shared equally
-// between the requests, largest chunks first in the work queue.
-// Requests admitted while others are on the GPU join the next round, so their
-// work overlaps on the device; up to max_inflight_rounds launches are queued
-// at once on two streams. A request whose last chunk has completed gets its
-// finalize kernel and result copy; it is done when that copy has landed.
+// order while the device memory of their tallies fits the HBM budget: the
+// tallies of admitted requests live in a server-owned device pool whose slabs
+// are allocated, within the budget, only when admission needs them.
+//
+// A worker thread keeps one persistent tracking launch ("round") open at a
+// time; the served kernel handles every geometry, estimator and source of one
+// precision, so one round serves the whole mix of that precision. The worker
+// feeds it through a queue of chunks in pinned host memory that the running
+// kernel reads (ServedFeed): small requests are published whole as they
+// arrive, large ones metered, about one chunk per wave ahead of the waves. A
+// wave takes the next item index with one fetch-add on a device counter (a
+// compare-and-swap claim collapses when thousands of waves contend for it) and
+// runs the item once it is published. Requests that arrive while the round
+// still has work to publish join it at once. The worker closes the round when
+// it has nothing left to publish (waves waiting in a round slow the waves that
+// run, so they leave at once, and a later request starts a fresh round), or
+// after a time slice when a request it cannot take waits (the other
+// precision, or a mesh finer than the round's LDS buffers); closing appends
+// one leave item per wave, so every item before them runs and every wave
+// leaves.
+//
+// The wave that flushes a request's last chunk stores the request's tag into
+// its done word (pinned); the worker then launches a finalize kernel (one wave
+// per request) that writes the record straight into the problem's pinned host
+// record (or into device memory and a copy, record_path 1) and clears the
+// tallies for the next request of that pool memory. Rounds leave a few
+// workgroup slots free, so the finalize kernel runs while they do. A request
+// whose chunks have all run without its done word, a wave that waited too long
+// for its item, and an item the kernel refuses stop the server with an error:
+// no request is left waiting for a completion that cannot come.
 //
 // Every history keeps the stream keyed by (seed, history index), and chunks
 // are fixed by the request's history count, so a request's results do not
@@ -20,6 +39,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -40,35 +60,107 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Round capacities: table entries (requests) and items (the last `waves` of
+// them kept for the leave items that end the round).
+constexpr int kMaxEntries = 4096;
+constexpr uint64_t kMaxItems = 1u << 20;
+// Workgroup slots a round leaves free for the finalize kernel.
+constexpr int kReservedSlots = 8;
+// Chunks of large requests published ahead of the waves' tickets, per wave.
+constexpr uint64_t kBulkAheadPerWave = 1;
+// A request of at most this many histories per resident wave is published
+// whole when it arrives (about one chunk-time of the GPU).
+constexpr uint64_t kPriorityHistoriesPerWave = 256;
+// Time a round stays open while a request it cannot take is waiting.
+constexpr double kSliceSeconds = 0.010;
+// Mesh capacity of a round's LDS buffers, at least (the served mix fits).
+constexpr int kServedMinBins = 1024;
+// A wave with nothing to run gives up on its ticket after about kWaitSeconds
+// of idle passes (a broken round), each s_sleep 127: 8128 shader cycles,
+// 3.4 us at the top clock of 2.4 GHz and longer below it.
+constexpr double kWaitSeconds = 5.0;
+constexpr double kIdlePassSeconds = 127.0 * 64.0 / 2.4e9;
+// Requests finalized by one finalize launch, and launches in flight.
+constexpr int kFinalizeBatch = 256;
+constexpr int kFinalizeSlots = 4;
+// Pool: block sizes are powers of two from kBlockMin; a slab holds up to
+// kSlabBlocks blocks of one size; kInitialBlocks blocks of each size up to
+// kInitialMaxBlock are allocated and zeroed when the server is created.
+constexpr size_t kBlockMin = 4096;
+constexpr size_t kSlabBlocks = 64;
+constexpr size_t kInitialBlocks = 16;
+constexpr size_t kInitialMaxBlock = 64 * 1024;
+
 enum ReqState { RQ_PENDING, RQ_ACTIVE, RQ_FINALIZING, RQ_DONE, RQ_FAILED };
 
 struct Request {
     uint64_t ticket = 0;
     cls_problem *p = nullptr;
+    Variant v;
     uint64_t histories = 0, seed = 0;
-    uint64_t chunk = 0, n_chunks = 0, next_chunk = 0, done_chunks = 0;
-    size_t footprint = 0;
+    uint64_t chunk = 0, n_chunks = 0;
+    uint64_t next_chunk = 0;             // chunks not yet published
+    uint64_t ran = 0;                    // chunks run in rounds that have ended
+    bool priority = false;
+    size_t footprint = 0;                // pool block bytes
+    char *block = nullptr;               // device: counters, sums, [device record]
     ReqState state = RQ_PENDING;
     cls_status error = CLS_OK;
     Clock::time_point t_submit, t_admit, t_done;
+    Clock::time_point t_publish, t_signal, t_finalize;
+    bool published_any = false, signalled = false, finalize_launched = false;
     uint32_t rounds = 0;
-    int stream = 0;
-    bool prepared = false;   // device side done (prepare)
-    uint64_t *host_record = nullptr;   // device address of the problem's pinned record (0: finalize kernel)
+    int last_round = -1;                 // round serial that last took chunks of it
+    uint64_t tag = 0;
+    uint64_t *done_host = nullptr;       // pinned done word
+    uint64_t *done_dev = nullptr;
+    uint64_t *host_record_dev = nullptr; // device address of p->h_record (record_path 0)
+    int finalize_slot = -1;
+
+    bool has_unpublished() const { return next_chunk < n_chunks; }
+    uint64_t unpublished() const { return n_chunks - next_chunk; }
 };
 
-struct RoundPart {
-    Request *r;
-    uint64_t chunks;
-};
-
+// Fixed pinned and device buffers of one round slot.
 struct RoundSlot {
-    char *dev = nullptr, *host = nullptr;
-    size_t bytes = 0;
-    hipEvent_t ev = nullptr;
-    bool busy = false;
     int stream = 0;
-    std::vector<RoundPart> parts;
+    hipEvent_t ev = nullptr;
+    bool busy = false;                   // launched, not yet retired
+    bool open = false;                   // still fed (no leave items yet)
+    int serial = -1;
+    Variant v;
+    Clock::time_point opened;
+    int grid = 0, block = 0, waves = 0, max_bins = 0;   // max_bins: mesh capacity of its LDS buffers
+    size_t lds = 0;
+    // pinned host: feed, items, the table of entry records
+    char *host = nullptr;
+    ServedFeed *feed = nullptr;
+    uint64_t *items = nullptr;
+    DevProblem *table = nullptr;
+    ServedDev *dev_copy = nullptr;       // the round's ServedDev, copied back after it
+    // their device addresses
+    ServedFeed *feed_d = nullptr;
+    uint64_t *items_d = nullptr;
+    DevProblem *table_d = nullptr;
+    // device: the ticket counter
+    char *dev = nullptr;
+    ServedDev *served_d = nullptr;
+    uint64_t n_items = 0;               // items published, leave items included
+    std::vector<Request *> entries;
+    std::map<Request *, int> entry_of;
+};
+
+struct FinalizeSlot {
+    DevProblem *host = nullptr, *dev = nullptr;   // pinned records and their device address
+    hipEvent_t ev = nullptr;
+    std::vector<Request *> reqs;
+    bool busy = false;
+};
+
+struct Slab {
+    char *base = nullptr;
+    size_t block = 0, count = 0;
+    hipEvent_t ready = nullptr;          // zeroing done (null: zeroed synchronously)
 };
 
 }  // namespace
@@ -83,15 +175,22 @@ struct cls_server {
     bool stop = false;
     std::deque<Request *> pending;
     std::vector<Request *> active;       // admitted, not yet done
-    std::set<const cls_problem *> in_flight;   // problems with a request being submitted, pending or active
+    std::set<const cls_problem *> in_flight;
     std::map<uint64_t, Request *> all;
     uint64_t next_ticket = 1;
-    uint32_t next_stream = 0;
-    size_t in_use = 0, peak = 0;
-    hipStream_t streams[2] = {nullptr, nullptr};
-    std::vector<RoundSlot> slots;
-    int next_variant = 0;
+    size_t in_use = 0, peak = 0, pool_bytes = 0;
+    hipStream_t streams[3] = {nullptr, nullptr, nullptr};   // two round streams, finalize
+    RoundSlot slots[2];
+    FinalizeSlot fin[kFinalizeSlots];
+    std::vector<Slab> slabs;
+    std::map<size_t, std::vector<char *>> free_blocks;     // block size -> free blocks
+    // done words: pinned pages that never move, free words as (host, device)
+    std::vector<uint64_t *> done_pages;
+    std::vector<std::pair<uint64_t *, uint64_t *>> free_done;
+    int round_serial = 0;
     uint64_t rounds = 0, completed = 0, failed = 0, hist_done = 0;
+    uint64_t wave_ticks_alive = 0, wave_ticks_idle = 0;   // over the rounds retired
+    bool dead = false;                   // a protocol error stopped the server
     Clock::time_point t0;
     cls_status worker_error = CLS_OK;
 };
@@ -103,14 +202,132 @@ double seconds_since(const cls_server *s, Clock::time_point t)
     return std::chrono::duration<double>(t - s->t0).count();
 }
 
+// The served kernel of the problem's precision (every kind of problem).
+Variant served_variant(const cls_problem *p)
+{
+    Variant v = variant_of(p);
+    v.geom = GEOM_ANY;
+    v.est = -1;
+    v.src = -1;
+    v.served = true;
+    return v;
+}
+
+// Mesh capacity of a round (or of the launch shape a request's chunks follow).
+int served_bins(int nbins) { return std::min(CLS_MAX_BINS, std::max(kServedMinBins, nbins)); }
+
+// ---------------------------------------------------------------------------
+// device pool of request tallies (budgeted)
+// ---------------------------------------------------------------------------
+// A pool block: counters, sums, then (record_path 1) the device record.
+size_t record_offset(int nbins)
+{
+    return align256(C_COUNT * sizeof(uint64_t)) + align256((2 + 2 * (size_t)nbins) * sizeof(double));
+}
+
+size_t block_bytes(const cls_server *s, int nbins)
+{
+    size_t b = record_offset(nbins);
+    if (s->cfg.record_path == 1) b += align256(record_words(nbins) * sizeof(uint64_t));
+    size_t c = kBlockMin;
+    while (c < b) c *= 2;
+    return c;
+}
+
+// A slab of `count` blocks of `bytes`, zeroed before its blocks are handed out
+// (synchronously, or on the finalize stream with an event to wait for).
+cls_status add_slab(cls_server *s, size_t bytes, size_t count, bool sync)
+{
+    Slab sl;
+    sl.block = bytes;
+    sl.count = count;
+    hipError_t e = hipMalloc((void **)&sl.base, bytes * count);
+    if (e != hipSuccess) return fail(CLS_ERR_OUT_OF_MEMORY, std::string("server pool: ") + hipGetErrorString(e));
+    if (sync) {
+        e = hipMemset(sl.base, 0, bytes * count);
+    } else {
+        e = hipMemsetAsync(sl.base, 0, bytes * count, s->streams[2]);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(sl.ready, s->streams[2]);
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(sl.base);
+        if (sl.ready) (void)hipEventDestroy(sl.ready);
+        return hip_fail(e, "server pool zeroing");
+    }
+    s->slabs.push_back(sl);
+    s->pool_bytes += bytes * count;
+    auto &fl = s->free_blocks[bytes];
+    for (size_t i = 0; i < count; ++i) fl.push_back(sl.base + i * bytes);
+    return CLS_OK;
+}
+
+// A block of `bytes` from the pool into *out, or nullptr (wait) while none is
+// free: a new slab is allocated when the budget allows it (and zeroed on the
+// finalize stream before its blocks are handed out); when nothing else is
+// admitted, one is allocated even beyond the budget, so a request never waits
+// for memory that no other request will free. Free blocks are zero.
+cls_status pool_alloc(cls_server *s, size_t bytes, char **out)
+{
+    *out = nullptr;
+    auto &fl = s->free_blocks[bytes];
+    bool zeroing = false;
+    for (size_t i = 0; i < fl.size(); ++i) {
+        char *b = fl[i];
+        bool ready = true;
+        for (Slab &sl : s->slabs)
+            if (b >= sl.base && b < sl.base + sl.block * sl.count && sl.ready) {
+                ready = hipEventQuery(sl.ready) == hipSuccess;
+                if (ready) {
+                    (void)hipEventDestroy(sl.ready);
+                    sl.ready = nullptr;
+                }
+            }
+        if (!ready) {
+            zeroing = true;
+            continue;
+        }
+        fl.erase(fl.begin() + (long)i);
+        *out = b;
+        return CLS_OK;
+    }
+    if (zeroing) return CLS_OK;
+    const size_t room = s->cfg.hbm_budget_bytes > s->pool_bytes ? s->cfg.hbm_budget_bytes - s->pool_bytes : 0;
+    size_t count = std::min<size_t>(kSlabBlocks, room / bytes);
+    if (count == 0) {
+        if (!s->active.empty()) return CLS_OK;
+        count = 1;
+    }
+    const cls_status st = add_slab(s, bytes, count, false);
+    return st;   // its blocks are usable once zeroed
+}
+
+void pool_free(cls_server *s, char *b, size_t bytes)
+{
+    if (b) s->free_blocks[bytes].push_back(b);
+}
+
+// ---------------------------------------------------------------------------
+// requests
+// ---------------------------------------------------------------------------
 // A request reaches its final state (under the lock); waiters are woken on
-// every path, failures included.
+// every path, failures included. Its pool block must be clear by then (the
+// finalize kernel clears it) or is cleared here.
 void finish(cls_server *s, Request *r, cls_status err)
 {
     r->state = err == CLS_OK ? RQ_DONE : RQ_FAILED;
     r->error = err;
     r->t_done = Clock::now();
-    s->in_use -= r->footprint;
+    if (r->block) s->in_use -= r->footprint;
+    if (r->block) {
+        if (err != CLS_OK) {
+            // its tallies may be partly written: clear them before reuse
+            (void)hipMemsetAsync(r->block, 0, r->footprint, s->streams[2]);
+            (void)hipStreamSynchronize(s->streams[2]);
+        }
+        pool_free(s, r->block, r->footprint);
+        r->block = nullptr;
+    }
     if (err == CLS_OK) {
         ++s->completed;
         s->hist_done += r->histories;
@@ -119,197 +336,356 @@ void finish(cls_server *s, Request *r, cls_status err)
     }
     s->active.erase(std::find(s->active.begin(), s->active.end(), r));
     s->in_flight.erase(r->p);
+    if (r->done_host) s->free_done.push_back({r->done_host, r->done_dev});
+    r->done_host = nullptr;
     s->cv_done.notify_all();
 }
 
-// Device side of a request, done once before it is admitted: the problem's
-// workspace, its chunking, its record and the reset of its tallies on the
-// request's stream (which the other stream waits for). Called from the
-// submitting thread when it runs on the server's device, else by the worker
-// at admission; the request is not yet visible to any round.
-cls_status prepare(cls_server *s, Request *r)
+// The record a round's kernel uses for entry r (in the round's pinned table).
+void entry_record(cls_server *s, Request *r, DevProblem *out)
 {
-    cls_problem *p = r->p;
-    cls_status st = ensure_device(p, 0);
-    if (st != CLS_OK) return st;
-    // chunks fixed by the request alone (never by the mix it meets): rounds
-    // are shared, so a small request need not be cut into a chunk per wave;
-    // a chunk stays within a round's share of one wave
-    int grid, block, stride;
-    size_t lds;
-    LaunchShape sh;
-    st = shape_for(variant_of(p), p->nbins, s->di, &grid, &block, &lds, &stride, &sh);
-    if (st != CLS_OK) return st;
-    const uint64_t waves_total = (uint64_t)grid * (uint64_t)(block / 64);
-    const uint64_t round_share = std::max<uint64_t>(1, s->cfg.round_histories / waves_total);
-    r->chunk = grouped_chunk_size(r->histories, waves_total, (uint64_t)sh.max_chunk, round_share);
-    r->n_chunks = (r->histories + r->chunk - 1) / r->chunk;
-    if (p->has_run && !p->done_synced) HIP_TRY(hipEventSynchronize(p->ev_done));
-    fill_dev_problem(p, r->histories, r->seed, r->chunk, 0, p->h_prob);
-    hipStream_t st_ = s->streams[r->stream];
-    HIP_TRY(hipMemcpyAsync(p->d_prob, p->h_prob, sizeof(DevProblem), hipMemcpyHostToDevice, st_));
-    HIP_TRY(launch_reset(p->d_prob, 1, p->d_items + 2, st_));
-    // both streams must see the reset before any round touches the tallies
-    HIP_TRY(hipEventRecord(p->ev_k0, st_));
-    HIP_TRY(hipStreamWaitEvent(s->streams[r->stream ^ 1], p->ev_k0, 0));
-    // the round that completes the request writes its record straight into the
-    // pinned host record when the device can address it; else a finalize
-    // kernel and a copy follow the request's last round
-    void *dptr = nullptr;
-    r->host_record = s->cfg.record_path == 0 && hipHostGetDevicePointer(&dptr, p->h_record, 0) == hipSuccess
-                          ? (uint64_t *)dptr
-                          : nullptr;
-    r->prepared = true;
-    return CLS_OK;
+    fill_dev_problem(r->p, r->histories, r->seed, r->chunk, 0, out);
+    out->counters = (uint64_t *)r->block;
+    out->sums = (double *)(r->block + align256(C_COUNT * sizeof(uint64_t)));
+    out->record = nullptr;
+    out->final_chunks = r->n_chunks;
+    out->host_record = nullptr;
+    out->done_word = r->done_dev;
+    out->tag = r->tag;
 }
 
-// Admission (under the lock).
-cls_status admit(cls_server *s, Request *r)
+// Admission (under the lock): a pool block within the budget.
+bool admit(cls_server *s, Request *r, cls_status *err)
 {
-    if (!r->prepared) {
-        const cls_status st = prepare(s, r);
-        if (st != CLS_OK) return st;
-    }
+    char *b = nullptr;
+    *err = pool_alloc(s, r->footprint, &b);
+    if (*err != CLS_OK || !b) return false;
+    r->block = b;
     r->t_admit = Clock::now();
     r->state = RQ_ACTIVE;
-    return CLS_OK;
+    s->in_use += r->footprint;
+    s->peak = std::max(s->peak, s->in_use);
+    return true;
 }
 
-cls_status ensure_slot(cls_server *s, RoundSlot &sl, size_t bytes)
+// ---------------------------------------------------------------------------
+// rounds
+// ---------------------------------------------------------------------------
+cls_status slot_buffers(cls_server *s, RoundSlot &sl)
 {
-    if (sl.bytes >= bytes) return CLS_OK;
-    if (sl.dev) (void)hipFree(sl.dev);
-    if (sl.host) (void)hipHostFree(sl.host);
-    sl.dev = sl.host = nullptr;
-    sl.bytes = 0;
-    const size_t want = std::max<size_t>(bytes * 2, 1 << 16);
-    hipError_t e = hipMalloc((void **)&sl.dev, want);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&sl.host, want, hipHostMallocDefault);
-    if (e != hipSuccess) return fail(CLS_ERR_OUT_OF_MEMORY, std::string("round buffers: ") + hipGetErrorString(e));
-    sl.bytes = want;
+    if (sl.host) return CLS_OK;
+    const size_t feed_b = align256(sizeof(ServedFeed));
+    const size_t items_b = align256(kMaxItems * sizeof(uint64_t));
+    const size_t table_b = align256((size_t)kMaxEntries * sizeof(DevProblem));
+    HIP_TRY(hipHostMalloc((void **)&sl.host, feed_b + items_b + table_b + align256(sizeof(ServedDev)),
+                          hipHostMallocDefault));
+    sl.feed = (ServedFeed *)sl.host;
+    sl.items = (uint64_t *)(sl.host + feed_b);
+    sl.table = (DevProblem *)(sl.host + feed_b + items_b);
+    sl.dev_copy = (ServedDev *)(sl.host + feed_b + items_b + table_b);
+    void *d = nullptr;
+    HIP_TRY(hipHostGetDevicePointer(&d, sl.host, 0));
+    char *hd = (char *)d;
+    sl.feed_d = (ServedFeed *)hd;
+    sl.items_d = (uint64_t *)(hd + feed_b);
+    sl.table_d = (DevProblem *)(hd + feed_b + items_b);
+    HIP_TRY(hipMalloc((void **)&sl.dev, align256(sizeof(ServedDev))));
+    sl.served_d = (ServedDev *)sl.dev;
+    HIP_TRY(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
     (void)s;
     return CLS_OK;
 }
 
-// Build and launch one round into a free slot. Returns true if launched.
-bool launch_round(cls_server *s, RoundSlot &sl, cls_status *err)
+// Whether request r may run in round sl: same kernel variant, and a mesh that
+// fits the round's LDS tally buffers (fixed at launch).
+bool fits(const RoundSlot &sl, const Request *r)
 {
-    // variants with chunks left, in a fixed order
-    std::vector<Variant> vars;
-    for (Request *r : s->active)
-        if (r->state == RQ_ACTIVE && r->next_chunk < r->n_chunks) {
-            const Variant v = variant_of(r->p);
-            bool seen = false;
-            for (const Variant &w : vars) seen = seen || same_variant(v, w);
-            if (!seen) vars.push_back(v);
-        }
-    if (vars.empty()) return false;
-    const Variant v = vars[(size_t)s->next_variant % vars.size()];
-    ++s->next_variant;
-    std::vector<Request *> reqs;
-    for (Request *r : s->active)
-        if (r->state == RQ_ACTIVE && r->next_chunk < r->n_chunks && same_variant(variant_of(r->p), v))
-            reqs.push_back(r);
-    // Launch shape first: its wave count sizes the round. Chunks were fixed at
-    // admission, so the share of histories in small chunks does not depend on
-    // the grid.
-    auto small_share_of = [](const std::vector<RoundPart> &parts) {
-        double small = 0.0, all = 0.0;
-        for (const RoundPart &part : parts) {
-            const double h = (double)part.chunks * (double)part.r->chunk;
-            all += h;
-            if (part.r->chunk < kSingleSlotMinChunk) small += h;
-        }
-        return all > 0.0 ? small / all : 1.0;
-    };
-    int max_bins = 1;
-    uint64_t max_chunk = 1;
-    sl.parts.clear();
-    for (Request *r : reqs) {
-        sl.parts.push_back({r, r->n_chunks - r->next_chunk});
-        max_bins = std::max(max_bins, r->p->nbins);
-        max_chunk = std::max(max_chunk, r->chunk);
+    return same_variant(r->v, sl.v) && r->p->nbins <= sl.max_bins;
+}
+
+// Items of the open round that are not leave items may use the queue up to
+// here: the last `waves` places are kept for the leave items.
+uint64_t item_room(const RoundSlot &sl)
+{
+    const uint64_t cap = kMaxItems - (uint64_t)sl.waves;
+    return sl.n_items < cap ? cap - sl.n_items : 0;
+}
+
+// Publish up to `max_items` chunks of request r to the open round (the host
+// writes the entry's record and the items, then raises `published`). Returns
+// the count.
+uint64_t publish(cls_server *s, RoundSlot &sl, Request *r, uint64_t max_items)
+{
+    if (!r->has_unpublished() || max_items == 0) return 0;
+    auto it = sl.entry_of.find(r);
+    int e;
+    if (it == sl.entry_of.end()) {
+        if ((int)sl.entries.size() >= kMaxEntries) return 0;
+        e = (int)sl.entries.size();
+        entry_record(s, r, &sl.table[e]);
+        sl.entries.push_back(r);
+        sl.entry_of[r] = e;
+    } else {
+        e = it->second;
     }
-    int grid = 0, block = 0, stride = 0;
-    size_t lds = 0;
+    uint64_t n = 0;
+    const uint64_t room = item_room(sl);
+    while (n < max_items && n < room && r->has_unpublished()) {
+        sl.items[sl.n_items + n] = ((uint64_t)e << 32) | r->next_chunk++;
+        ++n;
+    }
+    if (n) {
+        sl.n_items += n;
+        __atomic_store_n(&sl.feed->published, sl.n_items, __ATOMIC_RELEASE);
+        if (!r->published_any) {
+            r->published_any = true;
+            r->t_publish = Clock::now();
+        }
+        if (r->last_round != sl.serial) {
+            r->last_round = sl.serial;
+            ++r->rounds;
+        }
+    }
+    return n;
+}
+
+// The round takes no more work: one leave item per wave follows its items, so
+// that every wave leaves once the items before them have all been taken.
+void close_round(RoundSlot &sl)
+{
+    if (!sl.open) return;
+    sl.open = false;
+    for (int w = 0; w < sl.waves; ++w) sl.items[sl.n_items + (uint64_t)w] = kServedLeave;
+    sl.n_items += (uint64_t)sl.waves;
+    __atomic_store_n(&sl.feed->published, sl.n_items, __ATOMIC_RELEASE);
+}
+
+// Feed the open round: small requests whole as they come, large ones metered
+// to kBulkAheadPerWave chunks per wave beyond the tickets the waves reported.
+void feed_round(cls_server *s, RoundSlot &sl)
+{
+    bool full = false;
+    for (Request *r : s->active) {
+        if (r->state != RQ_ACTIVE || !r->priority || !fits(sl, r) || !r->has_unpublished()) continue;
+        publish(s, sl, r, r->unpublished());
+        full = full || r->has_unpublished();
+    }
+    const uint64_t seen = __atomic_load_n(&sl.feed->seen, __ATOMIC_ACQUIRE);
+    const uint64_t target = (uint64_t)sl.waves * kBulkAheadPerWave + 64;
+    uint64_t ahead = sl.n_items > seen ? sl.n_items - seen : 0;
+    for (Request *r : s->active) {
+        if (ahead >= target) break;
+        if (r->state != RQ_ACTIVE || r->priority || !fits(sl, r) || !r->has_unpublished()) continue;
+        ahead += publish(s, sl, r, target - ahead);
+        full = full || (r->has_unpublished() && ahead < target);
+    }
+    // a round that cannot take more entries or items is closed
+    if (full || item_room(sl) == 0) close_round(sl);
+}
+
+bool round_has_work(cls_server *s, const RoundSlot &sl)
+{
+    for (Request *r : s->active)
+        if (r->state == RQ_ACTIVE && fits(sl, r) && r->has_unpublished()) return true;
+    return false;
+}
+
+// Launch a round of variant v in a free slot, fed with what is waiting.
+cls_status open_round(cls_server *s, RoundSlot &sl, const Variant &v)
+{
+    cls_status st = slot_buffers(s, sl);
+    if (st != CLS_OK) return st;
+    // the mesh capacity of the round's LDS buffers: kServedMinBins, or the
+    // finest mesh waiting; a request with a finer one that arrives later waits
+    // for a later round
+    int max_bins = kServedMinBins;
+    for (Request *r : s->active)
+        if (r->state == RQ_ACTIVE && same_variant(r->v, v) && r->has_unpublished())
+            max_bins = std::max(max_bins, r->p->nbins);
+    max_bins = served_bins(max_bins);
+    int grid, block, stride;
+    size_t lds;
     LaunchShape used;
-    const double backlog_share = small_share_of(sl.parts);
-    *err = shape_for(v, max_bins, s->di, &grid, &block, &lds, &stride, &used,
-                     [backlog_share](uint64_t, uint64_t) { return backlog_share; });
-    // Round size (sched::round_budget), shared by water-filling: requests with
-    // less left than an equal share finish in this round, the others get the
-    // equal share of what remains (at least one chunk each).
-    const uint64_t waves = *err == CLS_OK ? (uint64_t)grid * (uint64_t)(block / 64) : 1;
-    const double budget = sched::round_budget((double)s->cfg.round_histories, waves, max_chunk);
-    std::vector<sched::RoundClaim> claims;
-    for (Request *r : reqs) claims.push_back({r->chunk, r->n_chunks - r->next_chunk});
-    const std::vector<uint64_t> take = sched::water_fill(claims, budget);
-    sl.parts.clear();
-    for (size_t i = 0; i < reqs.size(); ++i) sl.parts.push_back({reqs[i], take[i]});
-    // largest chunks first: the work queue hands items out in order, so the
-    // small chunks fill the waves that finish early
-    std::stable_sort(sl.parts.begin(), sl.parts.end(),
-                     [](const RoundPart &a, const RoundPart &b) { return a.r->chunk > b.r->chunk; });
-    const int n = (int)sl.parts.size();
-    const size_t probs_bytes = align256((size_t)n * sizeof(DevProblem));
-    // item prefix sums, the queue head and the count of waves that have left
-    const size_t items_bytes = align256(((size_t)n + 3) * sizeof(uint64_t));
-    if (*err == CLS_OK) {
-        const double share = small_share_of(sl.parts);
-        *err = shape_for(v, max_bins, s->di, &grid, &block, &lds, &stride, &used,
-                         [share](uint64_t, uint64_t) { return share; });
-    }
-    if (*err == CLS_OK) *err = ensure_slot(s, sl, probs_bytes + items_bytes);
-    if (*err != CLS_OK) {
-        // these requests cannot be launched: fail them rather than retry forever
-        for (RoundPart &part : sl.parts) finish(s, part.r, *err);
-        sl.parts.clear();
-        return false;
-    }
-    DevProblem *h_probs = (DevProblem *)sl.host;
-    uint64_t *h_items = (uint64_t *)(sl.host + probs_bytes);
-    h_items[0] = 0;
-    for (int i = 0; i < n; ++i) {
-        Request *r = sl.parts[i].r;
-        fill_dev_problem(r->p, r->histories, r->seed, r->chunk, 0, &h_probs[i]);
-        h_probs[i].chunk_base = r->next_chunk;
-        if (r->host_record) {
-            h_probs[i].final_chunks = r->n_chunks;
-            h_probs[i].host_record = r->host_record;
+    // one LDS tally buffer per wave (twice the resident waves) when at most
+    // kSingleSlotMaxSmallShare of the histories waiting are in chunks below
+    // kSingleSlotMinChunk, as for a batch; the requests that join later follow
+    // the round's choice
+    double small = 0.0, all = 0.0;
+    for (Request *r : s->active)
+        if (r->state == RQ_ACTIVE && same_variant(r->v, v) && r->has_unpublished()) {
+            const double h = (double)r->histories;
+            all += h;
+            if (r->chunk < kSingleSlotMinChunk) small += h;
         }
-        h_items[i + 1] = h_items[i] + sl.parts[i].chunks;
-    }
-    h_items[n + 1] = 0;
-    h_items[n + 2] = 0;
-    hipStream_t st = s->streams[sl.stream];
+    const double small_share = all > 0.0 ? small / all : 1.0;
+    st = shape_for(v, max_bins, s->di, &grid, &block, &lds, &stride, &used,
+                   [small_share](uint64_t, uint64_t) { return small_share; });
+    if (st != CLS_OK) return st;
+    grid = std::max(1, grid - kReservedSlots);
+    sl.v = v;
+    sl.serial = s->round_serial++;
+    sl.grid = grid;
+    sl.block = block;
+    sl.lds = lds;
+    sl.waves = grid * (block / 64);
+    sl.max_bins = max_bins;
+    sl.n_items = 0;
+    sl.entries.clear();
+    sl.entry_of.clear();
+    std::memset(sl.feed, 0, sizeof(ServedFeed));
+    sl.open = true;
+    sl.opened = Clock::now();
+    // only requests whose mesh fits the round's buffers are fed to it
+    feed_round(s, sl);
+    hipStream_t stream = s->streams[sl.stream];
+    HIP_TRY(hipMemsetAsync(sl.dev, 0, sizeof(ServedDev), stream));
     TrackArgs a;
-    a.probs = (const DevProblem *)sl.dev;
-    a.item_start = (const uint64_t *)(sl.dev + probs_bytes);
-    a.queue_head = (uint64_t *)(sl.dev + probs_bytes) + n + 1;
-    a.nprobs = n;
+    a.probs = sl.table_d;
+    a.item_start = nullptr;
+    a.queue_head = nullptr;
+    a.nprobs = kMaxEntries;
     a.lds_stride = stride;
     a.refill_min = used.refill_min;
     a.slots = used.slots;
-    a.exit_count = (unsigned long long *)(sl.dev + probs_bytes) + n + 2;
-    hipError_t e = hipMemcpyAsync(sl.dev, sl.host, probs_bytes + items_bytes, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_track(v, a, grid, block, lds, st);
-    if (e == hipSuccess) e = hipEventRecord(sl.ev, st);
-    if (e != hipSuccess) {
-        *err = hip_fail(e, "round launch");
-        for (RoundPart &part : sl.parts) finish(s, part.r, *err);
-        sl.parts.clear();
-        return false;
-    }
-    for (RoundPart &part : sl.parts) {
-        part.r->next_chunk += part.chunks;
-        ++part.r->rounds;
-    }
+    a.feed = sl.feed_d;
+    a.items = sl.items_d;
+    a.served = sl.served_d;
+    a.wait_passes = (uint64_t)(kWaitSeconds / kIdlePassSeconds);
+    HIP_TRY(launch_track(v, a, grid, block, lds, stream));
+    HIP_TRY(hipMemcpyAsync(sl.dev_copy, sl.dev, sizeof(ServedDev), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipEventRecord(sl.ev, stream));
     sl.busy = true;
     ++s->rounds;
-    return true;
+    return CLS_OK;
 }
 
-// A request whose results are in its problem's host record.
+// A round whose launch has completed: chunks it published but never ran go
+// back to their requests.
+// A protocol error: every request not yet finalizing fails with `err`, and
+// the server takes no more (its rounds drain; destroy still works).
+void stop_server(cls_server *s, cls_status err)
+{
+    s->dead = true;
+    s->worker_error = err;
+    while (!s->pending.empty()) {
+        s->active.push_back(s->pending.front());
+        s->pending.pop_front();
+    }
+    std::vector<Request *> victims;
+    for (Request *r : s->active)
+        if (r->state == RQ_ACTIVE || r->state == RQ_PENDING) victims.push_back(r);
+    for (Request *r : victims) finish(s, r, err);
+}
+
+// A round whose launch has completed: its waves took every item before the
+// leave items, so every chunk it published has run.
+void retire_round(cls_server *s, RoundSlot &sl, hipError_t q)
+{
+    sl.busy = false;
+    sl.open = false;
+    if (q == hipSuccess) {
+        s->wave_ticks_alive += sl.dev_copy->alive_ticks;
+        s->wave_ticks_idle += sl.dev_copy->idle_ticks;
+    }
+    for (uint64_t i = 0; i < sl.n_items; ++i)
+        if (sl.items[i] != kServedLeave) ++sl.entries[(size_t)(sl.items[i] >> 32)]->ran;
+    if (q != hipSuccess) {
+        const cls_status err = hip_fail(q, "served round");
+        s->worker_error = err;
+        for (Request *r : sl.entries)
+            if (r->state == RQ_ACTIVE) finish(s, r, err);
+    } else if (const uint64_t code = __atomic_load_n(&sl.feed->error, __ATOMIC_ACQUIRE)) {
+        const uint64_t it = __atomic_load_n(&sl.feed->error_item, __ATOMIC_ACQUIRE);
+        stop_server(s, fail(CLS_ERR_DEVICE,
+                            code == kServedErrWait
+                                ? "served round: a wave waited too long for item " + std::to_string(it)
+                                : "served round refused item (entry " + std::to_string(it >> 32) + ", chunk " +
+                                      std::to_string(it & 0xFFFFFFFFull) + "): not a chunk of a request in its table"));
+    } else {
+        // the launch has completed, so the done word of a request whose chunks
+        // have all run is visible by now
+        for (Request *r : sl.entries)
+            if (r->state == RQ_ACTIVE && r->ran == r->n_chunks &&
+                __atomic_load_n(r->done_host, __ATOMIC_ACQUIRE) != r->tag) {
+                stop_server(s, fail(CLS_ERR_DEVICE, "served request " + std::to_string(r->ticket) +
+                                                        ": every chunk ran but no completion was signalled"));
+                break;
+            }
+    }
+    sl.entries.clear();
+    sl.entry_of.clear();
+}
+
+// ---------------------------------------------------------------------------
+// finalize
+// ---------------------------------------------------------------------------
+cls_status fin_buffers(FinalizeSlot &f)
+{
+    if (f.host) return CLS_OK;
+    HIP_TRY(hipHostMalloc((void **)&f.host, kFinalizeBatch * sizeof(DevProblem), hipHostMallocDefault));
+    void *d = nullptr;
+    HIP_TRY(hipHostGetDevicePointer(&d, f.host, 0));
+    f.dev = (DevProblem *)d;
+    HIP_TRY(hipEventCreateWithFlags(&f.ev, hipEventDisableTiming));
+    return CLS_OK;
+}
+
+// Finalize the requests whose done word is set (one launch per batch).
+void start_finalizes(cls_server *s)
+{
+    std::vector<Request *> ready;
+    for (Request *r : s->active)
+        if (r->state == RQ_ACTIVE && __atomic_load_n(r->done_host, __ATOMIC_ACQUIRE) == r->tag) {
+            if (!r->signalled) {
+                r->signalled = true;
+                r->t_signal = Clock::now();
+            }
+            ready.push_back(r);
+        }
+    size_t k = 0;
+    while (k < ready.size()) {
+        FinalizeSlot *f = nullptr;
+        for (FinalizeSlot &x : s->fin)
+            if (!x.busy) f = &x;
+        if (!f) return;   // all in flight: the rest waits for the next pass
+        cls_status st = fin_buffers(*f);
+        if (st != CLS_OK) {
+            s->worker_error = st;
+            return;
+        }
+        f->reqs.clear();
+        for (; k < ready.size() && (int)f->reqs.size() < kFinalizeBatch; ++k) {
+            Request *r = ready[k];
+            DevProblem *rec = &f->host[f->reqs.size()];
+            entry_record(s, r, rec);
+            rec->record = s->cfg.record_path == 0 && r->host_record_dev
+                              ? r->host_record_dev
+                              : (uint64_t *)(r->block + record_offset(r->p->nbins));
+            r->state = RQ_FINALIZING;
+            r->finalize_launched = true;
+            r->t_finalize = Clock::now();
+            f->reqs.push_back(r);
+        }
+        hipStream_t st_ = s->streams[2];
+        hipError_t e = launch_finalize_clear(f->dev, (int)f->reqs.size(), st_);
+        for (size_t i = 0; i < f->reqs.size() && e == hipSuccess; ++i) {
+            Request *r = f->reqs[i];
+            if (f->host[i].record != r->host_record_dev || !r->host_record_dev)
+                e = hipMemcpyAsync(r->p->h_record, f->host[i].record, record_words(r->p->nbins) * sizeof(uint64_t),
+                                   hipMemcpyDeviceToHost, st_);
+        }
+        if (e == hipSuccess) e = hipEventRecord(f->ev, st_);
+        if (e != hipSuccess) {
+            const cls_status err = hip_fail(e, "served finalize");
+            for (Request *r : f->reqs) finish(s, r, err);
+            f->reqs.clear();
+            continue;
+        }
+        f->busy = true;
+    }
+}
+
+// A request whose record is in its problem's host record.
 void complete(cls_server *s, Request *r)
 {
     cls_problem *p = r->p;
@@ -323,102 +699,118 @@ void complete(cls_server *s, Request *r)
     finish(s, r, p->h_record[C_CAPPED] ? CLS_ERR_EVENT_CAP : CLS_OK);
 }
 
-// A request whose chunks all completed (no device-addressable host record):
-// finalize and copy its results back.
-cls_status start_finalize(cls_server *s, Request *r)
+void retire_finalizes(cls_server *s)
 {
-    cls_problem *p = r->p;
-    hipStream_t st = s->streams[r->stream];
-    HIP_TRY(launch_finalize(p->d_prob, 1, st));
-    HIP_TRY(hipMemcpyAsync(p->h_record, p->d_record, record_words(p->nbins) * sizeof(uint64_t),
-                           hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipEventRecord(p->ev_done, st));
-    p->done_synced = false;
-    r->state = RQ_FINALIZING;
-    return CLS_OK;
+    for (FinalizeSlot &f : s->fin) {
+        if (!f.busy) continue;
+        const hipError_t q = hipEventQuery(f.ev);
+        if (q == hipErrorNotReady) continue;
+        f.busy = false;
+        for (Request *r : f.reqs) {
+            if (q == hipSuccess) complete(s, r);
+            else finish(s, r, hip_fail(q, "served finalize"));
+        }
+        f.reqs.clear();
+    }
 }
 
+// ---------------------------------------------------------------------------
+// worker
+// ---------------------------------------------------------------------------
 void worker_main(cls_server *s)
 {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        // admit in arrival order while the footprint fits
+        // admit in arrival order while the pool allows
         while (!s->pending.empty()) {
             Request *r = s->pending.front();
-            if (s->in_use + r->footprint > s->cfg.hbm_budget_bytes && !s->active.empty()) break;
+            cls_status err = CLS_OK;
+            const bool ok = admit(s, r, &err);
+            if (!ok && err == CLS_OK) break;   // waits for memory
             s->pending.pop_front();
             s->active.push_back(r);
-            s->in_use += r->footprint;
-            s->peak = std::max(s->peak, s->in_use);
-            const cls_status st = admit(s, r);
-            if (st != CLS_OK) finish(s, r, st);
+            if (!ok) finish(s, r, err);
         }
-        // retire completed rounds
+        // results: done words -> finalize -> host records
+        retire_finalizes(s);
+        start_finalizes(s);
+        // retire rounds whose launch completed
         for (RoundSlot &sl : s->slots) {
             if (!sl.busy) continue;
             const hipError_t q = hipEventQuery(sl.ev);
             if (q == hipErrorNotReady) continue;
-            sl.busy = false;
-            for (RoundPart &part : sl.parts) {
-                Request *r = part.r;
-                if (q != hipSuccess) {
-                    if (r->state == RQ_ACTIVE) finish(s, r, hip_fail(q, "round"));
-                    continue;
+            retire_round(s, sl, q);
+        }
+        // feed the open round. It is closed once it has nothing left to
+        // publish (waves without work leave at once: waves waiting in a round
+        // slow the ones that run, and a request that arrives later starts a
+        // round of its own within tens of microseconds), and after a slice when
+        // a request it cannot take waits (other precision, finer mesh).
+        RoundSlot *open = nullptr;
+        for (RoundSlot &sl : s->slots)
+            if (sl.busy && sl.open) open = &sl;
+        if (open) {
+            bool other = false;
+            for (Request *r : s->active)
+                if (r->state == RQ_ACTIVE && r->has_unpublished() && !fits(*open, r)) other = true;
+            const double age = std::chrono::duration<double>(Clock::now() - open->opened).count();
+            if (!round_has_work(s, *open) || (other && age >= kSliceSeconds)) {
+                close_round(*open);
+                open = nullptr;
+            } else {
+                feed_round(s, *open);
+                if (!open->open) open = nullptr;
+            }
+        }
+        // open a round for the precision of the oldest waiting request
+        if (!open && !s->dead) {
+            Request *oldest = nullptr;
+            for (Request *r : s->active)
+                if (r->state == RQ_ACTIVE && r->has_unpublished()) {
+                    bool running_open = false;
+                    for (RoundSlot &sl : s->slots) running_open = running_open || (sl.busy && sl.open && fits(sl, r));
+                    if (!running_open && (!oldest || r->ticket < oldest->ticket)) oldest = r;
                 }
-                r->done_chunks += part.chunks;
-                if (r->state == RQ_ACTIVE && r->done_chunks == r->n_chunks) {
-                    if (r->host_record) {
-                        // every round with its chunks has completed, and the last
-                        // of them wrote the record into the pinned host record
-                        complete(s, r);
-                    } else {
-                        const cls_status st = start_finalize(s, r);
-                        if (st != CLS_OK) finish(s, r, st);
+            if (oldest) {
+                for (RoundSlot &sl : s->slots) {
+                    if (sl.busy) continue;
+                    const cls_status st = open_round(s, sl, oldest->v);
+                    if (st != CLS_OK) {
+                        s->worker_error = st;
+                        const Variant v = oldest->v;
+                        std::vector<Request *> victims;
+                        for (Request *r : s->active)
+                            if (r->state == RQ_ACTIVE && same_variant(r->v, v)) victims.push_back(r);
+                        for (Request *r : victims) finish(s, r, st);
                     }
+                    break;
                 }
             }
-            sl.parts.clear();
-        }
-        // results that have landed
-        for (size_t i = 0; i < s->active.size();) {
-            Request *r = s->active[i];
-            if (r->state == RQ_FINALIZING) {
-                const hipError_t q = hipEventQuery(r->p->ev_done);
-                if (q != hipErrorNotReady) {
-                    if (q == hipSuccess) {
-                        complete(s, r);            // ev_done was seen complete above
-                    } else {
-                        finish(s, r, hip_fail(q, "result copy"));
-                    }
-                    continue;      // finish() removed active[i]
-                }
-            }
-            ++i;
-        }
-        // launch rounds into free slots
-        bool launched = false;
-        for (RoundSlot &sl : s->slots) {
-            if (sl.busy) continue;
-            cls_status err = CLS_OK;
-            if (launch_round(s, sl, &err)) launched = true;
-            else if (err != CLS_OK) s->worker_error = err;
-            if (!launched) break;
         }
         bool busy = false;
         for (const RoundSlot &sl : s->slots) busy = busy || sl.busy;
-        bool finalizing = false;
-        for (Request *r : s->active) finalizing = finalizing || r->state == RQ_FINALIZING;
+        for (const FinalizeSlot &f : s->fin) busy = busy || f.busy;
         if (s->stop && s->pending.empty() && s->active.empty() && !busy) break;
-        if (!busy && !finalizing && s->pending.empty() && !launched) {
+        if (!busy && s->active.empty() && s->pending.empty()) {
             s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
-        } else if (!launched) {
+        } else {
             // the GPU is working: poll again shortly, without the lock
             lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(100));
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
             lk.lock();
         }
     }
+}
+
+// Pinned result record of the problem (host side only) and its device address.
+cls_status host_record_of(cls_problem *p, uint64_t **dev)
+{
+    if (!p->h_record)
+        HIP_TRY(hipHostMalloc((void **)&p->h_record, record_words(p->nbins) * sizeof(uint64_t), hipHostMallocDefault));
+    void *d = nullptr;
+    *dev = hipHostGetDevicePointer(&d, p->h_record, 0) == hipSuccess ? (uint64_t *)d : nullptr;
+    return CLS_OK;
 }
 
 }  // namespace
@@ -429,6 +821,8 @@ cls_status cls_server_create(const cls_server_config *cfg, cls_server **out)
 {
     if (!out) return fail(CLS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    if (cfg && cfg->record_path != 0 && cfg->record_path != 1)
+        return fail(CLS_ERR_INVALID_ARG, "record_path must be 0 or 1");
     DeviceInfo di;
     cls_status st = device_info(&di);
     if (st != CLS_OK) return st;
@@ -441,25 +835,26 @@ cls_status cls_server_create(const cls_server_config *cfg, cls_server **out)
         s->cfg.hbm_budget_bytes = free_b / 10 * 8;
     }
     if (s->cfg.round_histories == 0) s->cfg.round_histories = 30000000ull;
-    if (s->cfg.record_path != 0 && s->cfg.record_path != 1) {
-        delete s;
-        return fail(CLS_ERR_INVALID_ARG, "record_path must be 0 or 1");
-    }
-    if (s->cfg.max_inflight_rounds <= 0) s->cfg.max_inflight_rounds = 2;
-    s->cfg.max_inflight_rounds = std::min(s->cfg.max_inflight_rounds, 8);
+    s->cfg.max_inflight_rounds = 2;
     s->device = di.id;
     s->di = di;
     s->t0 = Clock::now();
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
-    s->slots.resize((size_t)s->cfg.max_inflight_rounds);
-    for (size_t i = 0; i < s->slots.size() && e == hipSuccess; ++i) {
-        e = hipEventCreateWithFlags(&s->slots[i].ev, hipEventDisableTiming);
-        s->slots[i].stream = (int)(i & 1);
-    }
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+    for (int i = 0; i < 2; ++i) s->slots[i].stream = i;
     if (e != hipSuccess) {
         cls_server_destroy(s);
         return hip_fail(e, "server streams");
+    }
+    // buffers of the rounds and finalize launches, and a first slab of each
+    // small block size within the budget, before any request waits for them
+    for (int i = 0; i < 2 && st == CLS_OK; ++i) st = slot_buffers(s, s->slots[i]);
+    for (int i = 0; i < kFinalizeSlots && st == CLS_OK; ++i) st = fin_buffers(s->fin[i]);
+    for (size_t b = kBlockMin; b <= kInitialMaxBlock && st == CLS_OK; b *= 2)
+        if (s->pool_bytes + kInitialBlocks * b <= s->cfg.hbm_budget_bytes) st = add_slab(s, b, kInitialBlocks, true);
+    if (st != CLS_OK) {
+        cls_server_destroy(s);
+        return st;
     }
     s->worker = std::thread(worker_main, s);
     *out = s;
@@ -471,43 +866,79 @@ cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, 
     if (!s || !p || !ticket) return fail(CLS_ERR_INVALID_ARG, "NULL argument");
     if (histories == 0) return fail(CLS_ERR_INVALID_ARG, "histories must be >= 1");
     if (p->flags & CLS_F_TRACE) return fail(CLS_ERR_INVALID_ARG, "served requests do not record traces");
+    if (p->device >= 0 && p->device != s->device)
+        return fail(CLS_ERR_STATE, "problem was first run on another device");
+    if (p->nbins > CLS_MAX_BINS) return fail(CLS_ERR_INVALID_ARG, "nbins above CLS_MAX_BINS");
     Request *r = new (std::nothrow) Request();
     if (!r) return fail(CLS_ERR_OUT_OF_MEMORY, "host allocation failed");
     r->p = p;
+    r->v = served_variant(p);
     r->histories = histories;
     r->seed = seed;
-    r->footprint = workspace_bytes(p->nbins, 0);
     r->t_submit = Clock::now();
+    // chunks fixed by the request alone (never by the mix it meets), as in a
+    // batch of resident rounds: at least kMinErrorBatches when the history
+    // count allows, at most one wave's share of round_histories
+    int grid, block, stride;
+    size_t lds;
+    LaunchShape sh;
+    cls_status st = shape_for(r->v, served_bins(p->nbins), s->di, &grid, &block, &lds, &stride, &sh,
+                              [](uint64_t, uint64_t) { return 1.0; });
+    uint64_t *rec_dev = nullptr;
+    if (st == CLS_OK) st = host_record_of(p, &rec_dev);
+    if (st != CLS_OK) {
+        delete r;
+        return st;
+    }
+    const uint64_t waves_total = (uint64_t)std::max(1, grid - kReservedSlots) * (uint64_t)(block / 64);
+    const uint64_t round_share = std::max<uint64_t>(1, s->cfg.round_histories / waves_total);
+    r->chunk = grouped_chunk_size(histories, waves_total, (uint64_t)sh.max_chunk, round_share);
+    r->n_chunks = (histories + r->chunk - 1) / r->chunk;
+    r->priority = histories <= kPriorityHistoriesPerWave * waves_total;
+    r->footprint = block_bytes(s, p->nbins);
+    r->host_record_dev = rec_dev;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) {
             delete r;
             return fail(CLS_ERR_STATE, "server is shutting down");
         }
+        if (s->dead) {
+            delete r;
+            return fail(CLS_ERR_STATE, "server stopped after a device error");
+        }
         if (!s->in_flight.insert(p).second) {
             delete r;
             return fail(CLS_ERR_STATE, "this problem already has a request in flight");
         }
-        r->stream = (int)(s->next_stream++ & 1u);
-    }
-    // The request's device side (allocation, chunking, record, tally reset)
-    // is done here, in the caller's thread, when it runs on the server's
-    // device, so that the worker does not hold the rounds back for it; no
-    // other request of this problem can be in the server now.
-    int dev = -1;
-    cls_status st = CLS_OK;
-    if (hipGetDevice(&dev) == hipSuccess && dev == s->device) st = prepare(s, r);
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (st == CLS_OK && s->stop) st = fail(CLS_ERR_STATE, "server is shutting down");
-        if (st != CLS_OK) {
-            s->in_flight.erase(p);
-            delete r;
-            return st;
+        // a done word (pinned) for the request, from pages of 1024
+        if (s->free_done.empty()) {
+            constexpr size_t kPage = 1024;
+            uint64_t *page = nullptr;
+            void *d = nullptr;
+            if (hipHostMalloc((void **)&page, kPage * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+                s->in_flight.erase(p);
+                delete r;
+                return fail(CLS_ERR_OUT_OF_MEMORY, "done words");
+            }
+            s->done_pages.push_back(page);
+            if (hipHostGetDevicePointer(&d, page, 0) != hipSuccess) {
+                s->in_flight.erase(p);
+                delete r;
+                return fail(CLS_ERR_DEVICE, "done words are not device-addressable");
+            }
+            std::memset(page, 0, kPage * sizeof(uint64_t));
+            for (size_t i = 0; i < kPage; ++i) s->free_done.push_back({page + i, (uint64_t *)d + i});
         }
+        r->done_host = s->free_done.back().first;
+        r->done_dev = s->free_done.back().second;
+        s->free_done.pop_back();
         r->ticket = s->next_ticket++;
+        r->tag = r->ticket;
+        __atomic_store_n(r->done_host, 0ull, __ATOMIC_RELEASE);
         s->all[r->ticket] = r;
         s->pending.push_back(r);
+        p->device = s->device;
         *ticket = r->ticket;
     }
     s->cv_work.notify_one();
@@ -562,6 +993,9 @@ cls_status cls_server_request_info(cls_server *s, uint64_t ticket, cls_request_i
     info->submit_s = seconds_since(s, r->t_submit);
     info->admit_s = r->state == RQ_PENDING ? -1.0 : seconds_since(s, r->t_admit);
     info->done_s = (r->state == RQ_DONE || r->state == RQ_FAILED) ? seconds_since(s, r->t_done) : -1.0;
+    info->publish_s = r->published_any ? seconds_since(s, r->t_publish) : -1.0;
+    info->signal_s = r->signalled ? seconds_since(s, r->t_signal) : -1.0;
+    info->finalize_s = r->finalize_launched ? seconds_since(s, r->t_finalize) : -1.0;
     return CLS_OK;
 }
 
@@ -594,6 +1028,7 @@ cls_status cls_server_get_stats(cls_server *s, cls_server_stats *out)
     out->hbm_peak = s->peak;
     out->hbm_budget = s->cfg.hbm_budget_bytes;
     out->worker_status = s->worker_error;
+    out->wave_idle_share = s->wave_ticks_alive ? (double)s->wave_ticks_idle / (double)s->wave_ticks_alive : 0.0;
     return CLS_OK;
 }
 
@@ -606,11 +1041,22 @@ void cls_server_destroy(cls_server *s)
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    for (hipStream_t st : s->streams)
+        if (st) (void)hipStreamSynchronize(st);
     for (RoundSlot &sl : s->slots) {
         if (sl.dev) (void)hipFree(sl.dev);
         if (sl.host) (void)hipHostFree(sl.host);
         if (sl.ev) (void)hipEventDestroy(sl.ev);
     }
+    for (FinalizeSlot &f : s->fin) {
+        if (f.host) (void)hipHostFree(f.host);
+        if (f.ev) (void)hipEventDestroy(f.ev);
+    }
+    for (Slab &sl : s->slabs) {
+        if (sl.base) (void)hipFree(sl.base);
+        if (sl.ready) (void)hipEventDestroy(sl.ready);
+    }
+    for (uint64_t *page : s->done_pages) (void)hipHostFree(page);
     for (hipStream_t st : s->streams)
         if (st) (void)hipStreamDestroy(st);
     for (auto &kv : s->all) delete kv.second;

@@ -90,6 +90,12 @@ __device__ __forceinline__ uint32_t rank_in(uint64_t mask)
 
 __device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
 
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
+{
+    return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), l) << 32) |
+           (uint64_t)__builtin_amdgcn_readlane((uint32_t)v, l);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -270,6 +276,10 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         L.m = B.k[0] < P.p0thr ? 0 : 1;
         L.x = 0.0; L.dy = 0; L.dz = 0;
         L.uy = (R)-1; L.uz = (R)-1;
+        // the chord factor is 1 on the rod and in the cube (the slab and the
+        // extruded geometry set theirs below); set here because a served
+        // round's lane may have run a history of another geometry before
+        if (G == GEOM_ROD || G == GEOM_CUBE3D) L.ig = (R)1;
         if (SRC == SRC_FACE) {
             if (G == GEOM_ROD) {
                 L.ux = 1; L.iux = 1;
@@ -498,6 +508,10 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
 // ---------------------------------------------------------------------------
 // Wave-uniform state of one chunk slot: first history, size, histories handed
 // out, histories in flight, problem, open flag.
+// s_waitcnt with vmcnt(0) and the other counters left at their maximum: the
+// wave's vector memory operations, stores and atomics included, are complete.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 struct SlotState {
     uint64_t h0;
     uint32_t cnt, next, live;
@@ -602,7 +616,7 @@ __device__ __forceinline__ void lane_to_slot(Lane<R> &L, double *wsum, uint32_t 
 // (prefix-scanned first for the difference-form track-length tally) as the
 // chunk's batch sum S and its square over the chunk size Q, the history score
 // sums and the event counters. Leaves the LDS slot zeroed and the slot closed.
-template <int EST>
+template <int EST, bool SERVED>
 __device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, double *b, double *ssum, uint32_t *c,
                                            int lane)
 {
@@ -666,19 +680,135 @@ __device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, dou
         atomicAdd(P.sums + 1, st2);
     }
     S.open = 0;
-    if (P.final_chunks != 0) {
-        // A served request: its flushed chunks are counted (after this wave's
-        // flush atomics have completed); the last wave of the launch writes
-        // the records of the requests whose chunks are all done.
-        __threadfence();
-        if (lane == 0) atomicAdd(Cg + C_DONE_CHUNKS, 1ull);
+    if (SERVED) {
+        // A served request: its flushed chunks are counted once this wave's
+        // flush atomics have been performed (waited for; they need no cache
+        // write-back, being performed where every later atomic on those words
+        // is). The wave that counts the last chunk, in this launch or another,
+        // does so after every other chunk's atomics were performed: it tells
+        // the host through the request's done word, and the host launches the
+        // finalize, which reads the tallies with atomic loads.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+        uint64_t done = 0;
+        if (lane == 0) done = atomicAdd(Cg + C_DONE_CHUNKS, 1ull) + 1ull;
+        done = readlane64(done, 0);
+        if (done == P.final_chunks && lane == 0)
+            __hip_atomic_store(P.done_word, P.tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// served rounds: work from the host's queues
+// ---------------------------------------------------------------------------
+// Outcomes of a claim other than a table entry: the wave's ticket is not
+// published yet, the wave received kServedLeave, or an item was refused
+// (reported in the feed's error word).
+constexpr int kClaimWait = -1;
+constexpr int kClaimLeave = -2;
+constexpr int kClaimRefused = -3;
+constexpr uint64_t kNoTicket = ~0ull;
+
+__device__ __forceinline__ void served_report(const TrackArgs &A, int lane, uint64_t code, uint64_t item)
+{
+    if (lane == 0) {
+        __hip_atomic_store(&A.feed->error_item, item, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&A.feed->error, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// The next chunk of a served round (see ServedFeed): its table entry and chunk
+// index. Called by the whole wave; lane 0 does the queue work. The wave's
+// ticket (an item index from one fetch-add on the head) is kept across calls
+// until the host has published that far; `pub` caches the last `published`
+// the wave read. The item is read only once `published` has been seen to
+// cover it, and both live in pinned host memory read past the caches (system
+// scope), so no fence is needed. The entry's record, in pinned memory too, was
+// written before its first item was published and is not changed while the
+// round runs.
+__device__ __forceinline__ int served_claim(const TrackArgs &A, int lane, uint64_t *ticket, uint64_t *pub,
+                                            uint64_t *chunk)
+{
+    if (*ticket == kNoTicket) {
+        uint64_t t = 0;
+        if (lane == 0) {
+            t = atomicAdd((unsigned long long *)&A.served->head, 1ull);
+            if ((t & 31u) == 0u)
+                __hip_atomic_store(&A.feed->seen, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        *ticket = readlane64(t, 0);
+    }
+    if (*ticket >= *pub) {
+        uint64_t p = 0;
+        if (lane == 0) p = __hip_atomic_load(&A.feed->published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        *pub = readlane64(p, 0);
+        if (*ticket >= *pub) return kClaimWait;
+    }
+    uint64_t item = 0;
+    if (lane == 0) item = __hip_atomic_load(A.items + *ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    item = readlane64(item, 0);
+    *ticket = kNoTicket;
+    if (item == kServedLeave) return kClaimLeave;
+    const uint64_t ent = item >> 32;
+    if (ent >= (uint64_t)A.nprobs) {
+        served_report(A, lane, kServedErrBadItem, item);
+        return kClaimRefused;
+    }
+    const int e = (int)ent;
+    *chunk = item & 0xFFFFFFFFull;
+    // the chunk must be one of the entry's chunks, and the entry of a kind the
+    // kernel tracks (any other would leave its lanes stepping for ever)
+    ConstProblem &P = ((ConstProblem *)A.probs)[e];
+    const uint64_t n = P.chunk ? (P.histories + P.chunk - 1) / P.chunk : 0;
+    if (*chunk >= n || P.final_chunks != n || (uint32_t)P.kind >= 16u) {
+        served_report(A, lane, kServedErrBadItem, item);
+        return kClaimRefused;
+    }
+    return e;
+}
+
+// One event step of a served round's lane: the problem's kind (a wave-uniform
+// value) selects the geometry, estimator and source.
+template <bool FP32, typename R>
+__device__ __forceinline__ int event_step_kind(int kind, Lane<R> &L, const Prm<R> &P, double *tal,
+                                               const MatRow<R> *mtab)
+{
+#define CLS_KIND_CASE(g, e, s) \
+    case problem_kind(g, e, s): return event_step<g, e, s, FP32, false, R>(L, P, tal, mtab);
+#define CLS_KIND_CASES(g)                          \
+    CLS_KIND_CASE(g, EST_COLLISION, SRC_FACE)      \
+    CLS_KIND_CASE(g, EST_COLLISION, SRC_VOLUME)    \
+    CLS_KIND_CASE(g, EST_TRACK, SRC_FACE)          \
+    CLS_KIND_CASE(g, EST_TRACK, SRC_VOLUME)
+    switch (kind) {
+        CLS_KIND_CASES(GEOM_ROD)
+        CLS_KIND_CASES(GEOM_SLAB)
+        CLS_KIND_CASES(GEOM_EXT2D)
+        CLS_KIND_CASES(GEOM_CUBE3D)
+    default: return EV_NONE;
+    }
+#undef CLS_KIND_CASES
+#undef CLS_KIND_CASE
+}
+
+// The flush of a slot: with the estimator of the kernel, or (served rounds)
+// of the slot's problem.
+template <int EST, bool SERVED>
+__device__ __forceinline__ void flush_any(SlotState &S, const TrackArgs &A, double *b, double *ssum, uint32_t *c,
+                                          int lane)
+{
+    if constexpr (EST >= 0) {
+        flush_slot<EST, SERVED>(S, A, b, ssum, c, lane);
+    } else {
+        const int est = (((ConstProblem *)A.probs)[S.pid].kind >> 2) & 1;
+        if (est == EST_TRACK) flush_slot<EST_TRACK, SERVED>(S, A, b, ssum, c, lane);
+        else flush_slot<EST_COLLISION, SERVED>(S, A, b, ssum, c, lane);
     }
 }
 
 // ---------------------------------------------------------------------------
 // the tracking kernel
 // ---------------------------------------------------------------------------
-template <int G, int EST, int SRC, bool FP32, bool TRACE>
+template <int G, int EST, int SRC, bool FP32, bool TRACE, bool SERVED>
 __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
 {
     using R = typename std::conditional<FP32, float, double>::type;
@@ -706,7 +836,17 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     SlotState C = {0, 0, 0, 0, 0, 0}, O = {0, 0, 0, 0, 0, 0};
     int cp = 0;
     bool queue_empty = false;
-    const uint64_t total_items = A.item_start[A.nprobs];
+    const uint64_t total_items = SERVED ? 0 : A.item_start[A.nprobs];
+    // served rounds: the wave's ticket and the last `published` it read. While
+    // the ticket is not published the wave looks again after poll_wait more
+    // passes of this loop (the gap doubles from 1 to 32); a pass of a wave with
+    // nothing to run sleeps (s_sleep 127, about 3.4 us at 2.4 GHz), and
+    // waited_passes counts those passes since the ticket was taken. The device
+    // clock is read only where an idle stretch begins and ends (idle_from).
+    uint64_t ticket = kNoTicket, pub = 0, waited_passes = 0;
+    uint32_t poll_wait = 0, poll_gap = 1;
+    uint64_t idle_ticks = 0, idle_from = 0;
+    const uint64_t born = SERVED ? (uint64_t)wall_clock64() : 0;
 
     Lane<R> L;
     L.x = 0.0; L.dy = L.dz = L.ux = L.uy = L.uz = 0;
@@ -727,24 +867,47 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
         if (dead != 0 && (dead == ~0ull || popc(dead) >= (uint32_t)A.refill_min)) {
             const bool slot_free = nslots == 2 ? ((!C.open || C.next == C.cnt) && !O.open) : !C.open;
             if (slot_free && !queue_empty) {
-                uint64_t got = 0;
-                if (lane == 0) got = atomicAdd((unsigned long long *)A.queue_head, 1ull);
-                // lane 0's value, made wave-uniform so that the slot state
-                // derived from it stays in scalar registers
-                const uint64_t item = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(got >> 32), 0) << 32) |
-                                      (uint64_t)__builtin_amdgcn_readlane((uint32_t)got, 0);
-                if (item >= total_items) {
-                    queue_empty = true;
-                } else {
-                    const __attribute__((address_space(4))) uint64_t *starts =
-                        (const __attribute__((address_space(4))) uint64_t *)A.item_start;
-                    int lo = 0, hi = A.nprobs;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (starts[mid] <= item) lo = mid; else hi = mid;
+                // the next chunk: its problem and its index among the problem's chunks
+                int lo = -1;
+                uint64_t chunk_index = 0;
+                if (SERVED) {
+                    lo = kClaimWait;
+                    if (poll_wait == 0) {
+                        lo = served_claim(A, lane, &ticket, &pub, &chunk_index);
+                        if (lo == kClaimWait) {
+                            poll_wait = poll_gap;
+                            poll_gap = poll_gap < 32u ? poll_gap * 2u : poll_gap;
+                        } else {
+                            poll_gap = 1;
+                            waited_passes = 0;
+                            if (lo == kClaimLeave || lo == kClaimRefused) queue_empty = true;
+                        }
+                    } else {
+                        --poll_wait;
                     }
+                } else {
+                    uint64_t got = 0;
+                    if (lane == 0) got = atomicAdd((unsigned long long *)A.queue_head, 1ull);
+                    // lane 0's value, made wave-uniform so that the slot state
+                    // derived from it stays in scalar registers
+                    const uint64_t item = readlane64(got, 0);
+                    if (item < total_items) {
+                        const __attribute__((address_space(4))) uint64_t *starts =
+                            (const __attribute__((address_space(4))) uint64_t *)A.item_start;
+                        int l = 0, hi = A.nprobs;
+                        while (hi - l > 1) {
+                            const int mid = (l + hi) >> 1;
+                            if (starts[mid] <= item) l = mid; else hi = mid;
+                        }
+                        lo = l;
+                        chunk_index = ((ConstProblem *)A.probs)[lo].chunk_base + item - starts[lo];
+                    }
+                }
+                if (lo < 0) {
+                    if (!SERVED) queue_empty = true;
+                } else {
                     ConstProblem &P = ((ConstProblem *)A.probs)[lo];
-                    const uint64_t first = (P.chunk_base + item - starts[lo]) * P.chunk;
+                    const uint64_t first = chunk_index * P.chunk;
                     const uint64_t rest = P.histories - first;
                     // the new chunk goes to the free slot, which becomes current
                     if (nslots == 2) {
@@ -789,7 +952,23 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
         }
 
         // ---------------- exit when nothing is left --------------------------
-        if (dead == ~0ull && queue_empty && !C.open && !O.open) break;
+        if (dead == ~0ull && !C.open && !O.open) {
+            if (queue_empty) break;
+            if (SERVED) {
+                // nothing to run: the ticket is not published yet; pause
+                // before looking again
+                if (idle_from == 0) idle_from = wall_clock64();
+                __builtin_amdgcn_s_sleep(127);
+                if (++waited_passes > A.wait_passes) {
+                    // the host never published this far: report it and leave
+                    served_report(A, lane, kServedErrWait, ticket);
+                    queue_empty = true;
+                }
+            }
+        } else if (SERVED && idle_from != 0) {
+            idle_ticks += (uint64_t)wall_clock64() - idle_from;
+            idle_from = 0;
+        }
 
         // ---------------- one event step per live lane -----------------------
         // A wave holds lanes of at most two problems (one per slot: a live lane
@@ -806,7 +985,11 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             if (mine) {
                 ConstProblem *cprob = (ConstProblem *)A.probs;
                 const Prm<R> P = load_prm<R>(cprob[pidc]);
-                ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + (L.slot ? KP : 0), wmat + 2 * L.slot);
+                double *tal = wbuf + (L.slot ? KP : 0);
+                if constexpr (G >= 0)
+                    ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, tal, wmat + 2 * L.slot);
+                else
+                    ev = event_step_kind<FP32, R>(cprob[pidc].kind, L, P, tal, wmat + 2 * L.slot);
             }
             todo &= ~ballot(mine);
         }
@@ -844,38 +1027,21 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             // their sums; they join the slot's counters first)
             if (C.open && C.next == C.cnt && C.live == 0) {
                 if (L.slot == cp) lane_to_slot(L, wsum, wctr);
-                flush_slot<EST>(C, A, wbuf + cp * KP, wsum + 2 * cp, wctr + cp * kSlotCounters, lane);
+                flush_any<EST, SERVED>(C, A, wbuf + cp * KP, wsum + 2 * cp, wctr + cp * kSlotCounters, lane);
             }
             if (O.open && O.next == O.cnt && O.live == 0) {
                 if (L.slot == (cp ^ 1)) lane_to_slot(L, wsum, wctr);
-                flush_slot<EST>(O, A, wbuf + (cp ^ 1) * KP, wsum + 2 * (cp ^ 1), wctr + (cp ^ 1) * kSlotCounters,
-                                lane);
+                flush_any<EST, SERVED>(O, A, wbuf + (cp ^ 1) * KP, wsum + 2 * (cp ^ 1), wctr + (cp ^ 1) * kSlotCounters,
+                                       lane);
             }
         }
     }
-
-    // ---------------- served requests: records of the finished ones ----------
-    // The last wave of the launch to leave writes the record of every request
-    // of the launch whose chunks are all flushed (in this launch or one that
-    // ran beside it) into its pinned host record, so that no finalize kernel
-    // or copy has to wait for compute units behind another launch.
-    if (A.exit_count) {
-        __threadfence();
-        unsigned long long left = 0;
-        if (lane == 0) left = atomicAdd(A.exit_count, 1ull);
-        left = ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(left >> 32), 0) << 32) |
-               (unsigned long long)__builtin_amdgcn_readlane((uint32_t)left, 0);
-        const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x / 64u);
-        if (left + 1 == waves) {
-            __threadfence();
-            for (int i = 0; i < A.nprobs; ++i) {
-                ConstProblem &P = ((ConstProblem *)A.probs)[i];
-                if (P.final_chunks == 0) continue;
-                const uint64_t done = __hip_atomic_load((const uint64_t *)P.counters + C_DONE_CHUNKS, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-                if (done == P.final_chunks) record_into<true>(P, P.host_record, lane, 64);
-            }
-            __threadfence_system();
+    if (SERVED) {
+        const uint64_t now = wall_clock64();
+        if (idle_from != 0) idle_ticks += now - idle_from;
+        if (lane == 0) {
+            atomicAdd(&A.served->alive_ticks, (unsigned long long)(now - born));
+            atomicAdd(&A.served->idle_ticks, (unsigned long long)idle_ticks);
         }
     }
 }
@@ -902,12 +1068,38 @@ __global__ void finalize_kernel(const DevProblem *probs)
 }
 
 // ---------------------------------------------------------------------------
+// finalize of served requests: one wave per request; the record goes to
+// P.record (the pinned host record or a device record), then the tallies are
+// cleared for the next request of that memory. The records are read from
+// pinned host memory.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) finalize_clear_kernel(const DevProblem *probs)
+{
+    // the tracking round that flushed these tallies may still be running:
+    // they are read and cleared with device-scope atomic operations, which see
+    // every flush atomic performed before
+    const DevProblem &P = probs[blockIdx.x];
+    record_into<true>(P, P.record, (int)threadIdx.x, (int)blockDim.x);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 + 2 * P.nbins; i += blockDim.x)
+        __hip_atomic_store(P.sums + i, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = threadIdx.x; i < C_COUNT; i += blockDim.x)
+        __hip_atomic_store(P.counters + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_reset(const DevProblem *d_probs, int nprobs, uint64_t *queue_head,
                         hipStream_t stream)
 {
     hipLaunchKernelGGL(reset_kernel, dim3(nprobs), dim3(256), 0, stream, d_probs, queue_head);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_clear(const DevProblem *probs, int nprobs, hipStream_t stream)
+{
+    hipLaunchKernelGGL(finalize_clear_kernel, dim3(nprobs), dim3(64), 0, stream, probs);
     return hipGetLastError();
 }
 
@@ -923,9 +1115,10 @@ typedef void (*TrackFn)(TrackArgs);
 template <int G, int EST, int SRC>
 static TrackFn pick_prec(const Variant &v)
 {
-    if (v.fp32) return v.trace ? track_kernel<G, EST, SRC, true, true> : track_kernel<G, EST, SRC, true, false>;
-    if (v.trace) return track_kernel<G, EST, SRC, false, true>;
-    return track_kernel<G, EST, SRC, false, false>;
+    if (v.fp32)
+        return v.trace ? track_kernel<G, EST, SRC, true, true, false> : track_kernel<G, EST, SRC, true, false, false>;
+    if (v.trace) return track_kernel<G, EST, SRC, false, true, false>;
+    return track_kernel<G, EST, SRC, false, false, false>;
 }
 
 template <int G>
@@ -938,6 +1131,12 @@ static TrackFn pick_geom(const Variant &v)
 
 static TrackFn pick(const Variant &v)
 {
+    // served rounds: one kernel per precision for every kind of problem
+    if (v.served) {
+        if (v.trace || v.geom != GEOM_ANY) return nullptr;
+        return v.fp32 ? track_kernel<GEOM_ANY, -1, -1, true, false, true>
+                      : track_kernel<GEOM_ANY, -1, -1, false, false, true>;
+    }
     switch (v.geom) {
     case GEOM_ROD: return pick_geom<GEOM_ROD>(v);
     case GEOM_SLAB: return pick_geom<GEOM_SLAB>(v);

@@ -2,16 +2,16 @@
 variance of Section 5).
 
 A mixed stream of rod, extruded-2D and cube requests (10 to 1000 bins, FP64 and FP32)
-goes through the continuous-batching server. The launch shape is narrowed (256 waves,
-chunks of at most 256 histories) so that rounds hold ~4e5 histories and the large
-requests run over several rounds next to the small ones.
+goes through the continuous-batching server, whose rounds run one kernel per precision
+for every kind of problem. The launch shape is narrowed (256 waves, chunks of at most
+256 histories) so that the large requests run for many chunks next to the small ones.
   - FP64 requests follow the oracle's random streams: the counts equal the oracle's
     and the flux agrees to 1e-9 (summation order only);
   - FP32 requests agree with oracle runs on independent seeds within 4 combined sigma
     (T, R, A, total flux) and by the binomial per-bin 4-sigma rule;
-  - the records that the tracking kernel writes into pinned host memory equal the
-    records of the finalize-kernel path (record_path = 1) for the same requests,
-    errors (sigma_*, flux_sigma) included.
+  - the records written straight into pinned host memory equal those written to
+    device memory and copied (record_path = 1) for the same requests, errors
+    (sigma_*, flux_sigma) included.
 All GPU calls go through the C ABI."""
 from __future__ import annotations
 
@@ -95,9 +95,10 @@ def test_served_requests_match_the_oracle(cls):
     finally:
         cls.cls_set_launch_config(0, 0, 0, 0)
     print("rounds", stats["rounds"], "per request", rounds, flush=True)
-    # the large requests ran over several rounds, sharing them with the small ones
-    assert all(r > 1 for (s, _), r in zip(mix, rounds) if s.histories >= 1_000_000)
+    # rounds were shared between requests, and each precision had rounds of
+    # its own (the round of one precision is closed for the other)
     assert sum(rounds) > stats["rounds"]
+    assert stats["rounds"] >= 2
     n_bins_bad = n_bins = 0
     for (s, fp32), (t, flux, fsig), (tf, fluxf, fsigf) in zip(mix, res, res_fin):
         g = tallies_dict(t)
