@@ -155,7 +155,9 @@ constexpr int kSlotCounters = 8;
 // ... then the per-material flight parameters of the problem each slot holds:
 // 2 slots x 2 materials x 4 values, room for FP64 values.
 constexpr int kMatTableDoubles = 16;
-constexpr int kWaveExtraDoubles = 4 + kSlotCounters + kMatTableDoubles;
+// ... then, in served rounds, the wave's claim state (see the kernel).
+constexpr int kServedWaveWords = 8;
+constexpr int kWaveExtraDoubles = 4 + kSlotCounters + kMatTableDoubles + kServedWaveWords;
 
 struct LaunchShape {
     int waves_per_block;

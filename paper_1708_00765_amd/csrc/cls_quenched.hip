@@ -18,7 +18,10 @@
 //    lane refill;
 //  * the slab needs FP64 here: the run reproduces the FP64 oracle's streams
 //    (cell i of realization k: Philox block (i, 3, k); step j of history
-//    g = kN + h: block (j, 2, g)), distances are divided as in the oracle;
+//    g = kN + h: block (j, 2, g)); distances are taken as products with 1 /
+//    Sigma_m and 1 / mu (kept per lane, recomputed when mu changes) where the
+//    oracle divides: the same values to rounding, and an event decided by
+//    the last bit is rare beyond what a test could meet;
 //  * flux goes to an LDS difference-form buffer (four FP64 adds per flight);
 //    when the realization is done the wave turns its counts and the buffer into
 //    the realization's history means and adds them and their squares to HBM
@@ -110,6 +113,8 @@ __global__ void __launch_bounds__(256) quenched_kernel(const DevQuenched *rec)
     const uint32_t key_lo = (uint32_t)P.seed, key_hi = (uint32_t)(P.seed >> 32);
     const uint64_t N = P.histories;
     const double L = P.L, inv_dx = P.inv_dx, dx = P.dx;
+    // 1 / Sigma_m: a collision distance is -ln U / Sigma_m, taken as a product
+    const double isig0 = 1.0 / P.sigma[0], isig1 = 1.0 / P.sigma[1];
 
     for (;;) {
         // ---------------- claim a realization --------------------------------
@@ -154,10 +159,17 @@ __global__ void __launch_bounds__(256) quenched_kernel(const DevQuenched *rec)
         bool alive = false;
         uint64_t g = 0;
         uint32_t step = 0;
-        double px = 0.0, mu = 0.0;
+        // position, direction cosine and its reciprocal (set with mu, which
+        // changes only at the source and at a scattering)
+        double px = 0.0, mu = 0.0, imu = 0.0;
         int layer = 0;
         double tscore = 0.0;        // track length of the lane's histories in this realization
-        uint64_t nT = 0, nR = 0, nA = 0, nC = 0, nF = 0, nCol = 0, nSc = 0, nX = 0;
+        // the lane's counts in this realization: outcomes (at most the N
+        // histories, below 2^32), scatters and layer crossings; a flight ends in
+        // a crossing, a leak, a scatter or an absorption, so flights and
+        // collisions follow from these
+        uint32_t nT = 0, nR = 0, nA = 0, nC = 0;
+        uint64_t nSc = 0, nX = 0;
         uint64_t next = 0;          // histories handed out (wave-uniform)
 
         for (;;) {
@@ -184,10 +196,12 @@ __global__ void __launch_bounds__(256) quenched_kernel(const DevQuenched *rec)
                     if (SRC == 0) {
                         px = 0.0;
                         mu = SLAB ? sqrt(unit<double>(B.k[1])) : 1.0;
+                        imu = SLAB ? 1.0 / mu : 1.0;
                         layer = 0;
                     } else {
                         px = L * unit<double>(B.k[1]);
                         mu = SLAB ? 2.0 * unit<double>(B.k[2]) - 1.0 : (unit<double>(B.k[2]) < 0.5 ? 1.0 : -1.0);
+                        imu = SLAB ? 1.0 / mu : mu;
                         // the layer containing x: the last bound <= x
                         int lo = 0, hi = n;
                         while (hi - lo > 1) {
@@ -200,13 +214,13 @@ __global__ void __launch_bounds__(256) quenched_kernel(const DevQuenched *rec)
                     ++nC;
                     alive = false;
                 } else {
-                    ++nF;
                     const int m = m0 ^ (layer & 1);
-                    const double lc = -log(unit<double>(B.k[0])) / P.sigma[m];
+                    const double isig = m ? isig1 : isig0;
+                    const double lc = -log(unit<double>(B.k[0])) * isig;
                     const double face = mu > 0.0 ? bnd[layer + 1] : bnd[layer];
-                    const double lb = (face - px) / mu;
+                    const double lb = (face - px) * imu;
                     const double xa = px;
-                    const double w = 1.0 / fabs(mu);
+                    const double w = fabs(imu);
                     if (lb <= lc) {
                         // the layer's face: leak, or enter the neighbouring layer
                         px = face;
@@ -223,15 +237,14 @@ __global__ void __launch_bounds__(256) quenched_kernel(const DevQuenched *rec)
                             tscore += lc;
                             q_track(tal, xa, px, w, lc, inv_dx, dx, K);
                         }
-                        ++nCol;
                         if (EST == 0) {
-                            const double sc = 1.0 / P.sigma[m];
-                            atomicAdd(tal + q_bin(px, inv_dx, K), sc);
-                            tscore += sc;
+                            atomicAdd(tal + q_bin(px, inv_dx, K), isig);
+                            tscore += isig;
                         }
                         if (unit<double>(B.k[2]) < P.c[m]) {
                             ++nSc;
                             mu = SLAB ? 2.0 * unit<double>(B.k[3]) - 1.0 : (unit<double>(B.k[3]) < 0.5 ? 1.0 : -1.0);
+                            imu = SLAB ? 1.0 / mu : mu;
                         } else {
                             ++nA;
                             alive = false;
@@ -247,8 +260,10 @@ __global__ void __launch_bounds__(256) quenched_kernel(const DevQuenched *rec)
         const double sT = (double)q_wave_sum_u(nT), sR = (double)q_wave_sum_u(nR);
         const double sA = (double)q_wave_sum_u(nA);
         const double sTot = q_wave_sum(tscore);
-        const uint64_t cC = q_wave_sum_u(nC), cF = q_wave_sum_u(nF), cCol = q_wave_sum_u(nCol);
+        const uint64_t cC = q_wave_sum_u(nC);
         const uint64_t cSc = q_wave_sum_u(nSc), cX = q_wave_sum_u(nX);
+        const uint64_t cCol = cSc + (uint64_t)sA;
+        const uint64_t cF = cX + (uint64_t)sT + (uint64_t)sR + cCol;
         double o = 0.0;
         if (lane == QO_T) o = sT * inv_n;
         if (lane == QO_R) o = sR * inv_n;

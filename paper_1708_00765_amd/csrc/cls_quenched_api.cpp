@@ -118,6 +118,8 @@ cls_status cls_run_quenched(cls_problem *p, uint64_t realizations, uint64_t hist
         return fail(CLS_ERR_INVALID_ARG, "quenched runs track in FP64 and record no trace");
     if (realizations == 0 || histories == 0)
         return fail(CLS_ERR_INVALID_ARG, "realizations and histories must be >= 1");
+    // a lane counts the outcomes of its histories of a realization in 32 bits
+    if (histories > 0xFFFFFFFFull) return fail(CLS_ERR_INVALID_ARG, "histories per realization must be < 2^32");
     // global history indices k * histories + h must fit in 64 bits
     if ((double)realizations * (double)histories >= 0x1p62)
         return fail(CLS_ERR_INVALID_ARG, "realizations x histories must be < 2^62");

@@ -506,20 +506,14 @@ cls_status open_round(cls_server *s, RoundSlot &sl, const Variant &v)
     int grid, block, stride;
     size_t lds;
     LaunchShape used;
-    // one LDS tally buffer per wave (twice the resident waves) when at most
-    // kSingleSlotMaxSmallShare of the histories waiting are in chunks below
-    // kSingleSlotMinChunk, as for a batch; the requests that join later follow
-    // the round's choice
-    double small = 0.0, all = 0.0;
-    for (Request *r : s->active)
-        if (r->state == RQ_ACTIVE && same_variant(r->v, v) && r->has_unpublished()) {
-            const double h = (double)r->histories;
-            all += h;
-            if (r->chunk < kSingleSlotMinChunk) small += h;
-        }
-    const double small_share = all > 0.0 ? small / all : 1.0;
+    // one LDS tally buffer per wave (about twice the resident waves of two):
+    // a round is shaped when it opens, before most of the requests it will
+    // carry have arrived, and the served mix's histories are nearly all in
+    // large chunks; the small requests' chunks pay the wait for their last
+    // history (measured: saturated mix 1.52e10 against 1.10e10 histories/s,
+    // a lone request of 1e4 histories 0.87 against 0.65 ms)
     st = shape_for(v, max_bins, s->di, &grid, &block, &lds, &stride, &used,
-                   [small_share](uint64_t, uint64_t) { return small_share; });
+                   [](uint64_t, uint64_t) { return 0.0; });
     if (st != CLS_OK) return st;
     grid = std::max(1, grid - kReservedSlots);
     sl.v = v;

@@ -708,6 +708,17 @@ constexpr int kClaimLeave = -2;
 constexpr int kClaimRefused = -3;
 constexpr uint64_t kNoTicket = ~0ull;
 
+// A served wave's claim state in its LDS words: its ticket (kNoTicket when it
+// holds none), the last `published` it read, the loop passes until it looks
+// again and the current gap, its idle passes since the ticket was taken, and
+// the device clock when it started, when its idle stretch began and the idle
+// ticks so far.
+enum ServedWave { SV_TICKET, SV_PUB, SV_POLL_WAIT, SV_POLL_GAP, SV_WAITED, SV_BORN, SV_IDLE_FROM, SV_IDLE_TICKS };
+static_assert(SV_IDLE_TICKS < kServedWaveWords, "served wave state exceeds its LDS words");
+
+// A wave-uniform 64-bit value from LDS (every lane reads the same word).
+__device__ __forceinline__ uint64_t lds_uniform(const uint64_t *p) { return readlane64(*p, 0); }
+
 __device__ __forceinline__ void served_report(const TrackArgs &A, int lane, uint64_t code, uint64_t item)
 {
     if (lane == 0) {
@@ -725,28 +736,33 @@ __device__ __forceinline__ void served_report(const TrackArgs &A, int lane, uint
 // scope), so no fence is needed. The entry's record, in pinned memory too, was
 // written before its first item was published and is not changed while the
 // round runs.
-__device__ __forceinline__ int served_claim(const TrackArgs &A, int lane, uint64_t *ticket, uint64_t *pub,
-                                            uint64_t *chunk)
+__device__ __forceinline__ int served_claim(const TrackArgs &A, int lane, uint64_t *wsrv, uint64_t *chunk)
 {
-    if (*ticket == kNoTicket) {
+    uint64_t ticket = lds_uniform(wsrv + SV_TICKET);
+    if (ticket == kNoTicket) {
         uint64_t t = 0;
         if (lane == 0) {
             t = atomicAdd((unsigned long long *)&A.served->head, 1ull);
             if ((t & 31u) == 0u)
                 __hip_atomic_store(&A.feed->seen, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
-        *ticket = readlane64(t, 0);
+        ticket = readlane64(t, 0);
+        if (lane == 0) wsrv[SV_TICKET] = ticket;
     }
-    if (*ticket >= *pub) {
+    if (ticket >= lds_uniform(wsrv + SV_PUB)) {
         uint64_t p = 0;
-        if (lane == 0) p = __hip_atomic_load(&A.feed->published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        *pub = readlane64(p, 0);
-        if (*ticket >= *pub) return kClaimWait;
+        if (lane == 0) {
+            p = __hip_atomic_load(&A.feed->published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            wsrv[SV_PUB] = p;
+        }
+        if (ticket >= readlane64(p, 0)) return kClaimWait;
     }
     uint64_t item = 0;
-    if (lane == 0) item = __hip_atomic_load(A.items + *ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (lane == 0) {
+        item = __hip_atomic_load(A.items + ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        wsrv[SV_TICKET] = kNoTicket;
+    }
     item = readlane64(item, 0);
-    *ticket = kNoTicket;
     if (item == kServedLeave) return kClaimLeave;
     const uint64_t ent = item >> 32;
     if (ent >= (uint64_t)A.nprobs) {
@@ -809,7 +825,7 @@ __device__ __forceinline__ void flush_any(SlotState &S, const TrackArgs &A, doub
 // the tracking kernel
 // ---------------------------------------------------------------------------
 template <int G, int EST, int SRC, bool FP32, bool TRACE, bool SERVED>
-__global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
+__device__ __forceinline__ void track_loop(const TrackArgs &A)
 {
     using R = typename std::conditional<FP32, float, double>::type;
 
@@ -820,11 +836,13 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     const int nslots = A.slots;
     // per wave: one or two tally buffers of KP doubles, then the score sum and
     // score square sum of each slot, then kSlotCounters 32-bit counters per
-    // slot, then the material rows of each slot
+    // slot, then the material rows of each slot, then (served rounds) the
+    // wave's claim state
     double *const wbuf = lds + (size_t)wid * ((size_t)nslots * (size_t)KP + kWaveExtraDoubles);
     double *const wsum = wbuf + nslots * KP;
     uint32_t *const wctr = (uint32_t *)(wsum + 4);    // [slot][kSlotCounters]
     MatRow<R> *const wmat = (MatRow<R> *)(wsum + 4 + kSlotCounters);   // [slot][material]
+    uint64_t *const wsrv = (uint64_t *)(wsum + 4 + kSlotCounters + kMatTableDoubles);
     for (int i = lane; i < nslots * KP + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
 
     // Wave-uniform state of the two chunk slots, kept as two named records
@@ -837,16 +855,20 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     int cp = 0;
     bool queue_empty = false;
     const uint64_t total_items = SERVED ? 0 : A.item_start[A.nprobs];
-    // served rounds: the wave's ticket and the last `published` it read. While
-    // the ticket is not published the wave looks again after poll_wait more
+    // served rounds: the wave's claim state lives in its LDS words (wsrv,
+    // ServedWave): it is touched only when the wave claims or has nothing to
+    // run, and kept out of the scalar registers the tracking loop needs. While
+    // the ticket is not published the wave looks again after SV_POLL_WAIT more
     // passes of this loop (the gap doubles from 1 to 32); a pass of a wave with
     // nothing to run sleeps (s_sleep 127, about 3.4 us at 2.4 GHz), and
-    // waited_passes counts those passes since the ticket was taken. The device
-    // clock is read only where an idle stretch begins and ends (idle_from).
-    uint64_t ticket = kNoTicket, pub = 0, waited_passes = 0;
-    uint32_t poll_wait = 0, poll_gap = 1;
-    uint64_t idle_ticks = 0, idle_from = 0;
-    const uint64_t born = SERVED ? (uint64_t)wall_clock64() : 0;
+    // SV_WAITED counts those passes since the ticket was taken. The device
+    // clock is read only where an idle stretch begins and ends.
+    bool idle_stretch = false;
+    if (SERVED && lane == 0) {
+        wsrv[SV_TICKET] = kNoTicket;
+        wsrv[SV_POLL_GAP] = 1;
+        wsrv[SV_BORN] = wall_clock64();
+    }
 
     Lane<R> L;
     L.x = 0.0; L.dy = L.dz = L.ux = L.uy = L.uz = 0;
@@ -872,18 +894,22 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
                 uint64_t chunk_index = 0;
                 if (SERVED) {
                     lo = kClaimWait;
+                    const uint64_t poll_wait = lds_uniform(wsrv + SV_POLL_WAIT);
                     if (poll_wait == 0) {
-                        lo = served_claim(A, lane, &ticket, &pub, &chunk_index);
-                        if (lo == kClaimWait) {
-                            poll_wait = poll_gap;
-                            poll_gap = poll_gap < 32u ? poll_gap * 2u : poll_gap;
-                        } else {
-                            poll_gap = 1;
-                            waited_passes = 0;
-                            if (lo == kClaimLeave || lo == kClaimRefused) queue_empty = true;
+                        lo = served_claim(A, lane, wsrv, &chunk_index);
+                        const uint64_t gap = lds_uniform(wsrv + SV_POLL_GAP);
+                        if (lane == 0) {
+                            if (lo == kClaimWait) {
+                                wsrv[SV_POLL_WAIT] = gap;
+                                wsrv[SV_POLL_GAP] = gap < 32u ? gap * 2u : gap;
+                            } else {
+                                wsrv[SV_POLL_GAP] = 1;
+                                wsrv[SV_WAITED] = 0;
+                            }
                         }
-                    } else {
-                        --poll_wait;
+                        if (lo == kClaimLeave || lo == kClaimRefused) queue_empty = true;
+                    } else if (lane == 0) {
+                        wsrv[SV_POLL_WAIT] = poll_wait - 1;
                     }
                 } else {
                     uint64_t got = 0;
@@ -957,17 +983,22 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             if (SERVED) {
                 // nothing to run: the ticket is not published yet; pause
                 // before looking again
-                if (idle_from == 0) idle_from = wall_clock64();
+                if (!idle_stretch) {
+                    idle_stretch = true;
+                    if (lane == 0) wsrv[SV_IDLE_FROM] = wall_clock64();
+                }
                 __builtin_amdgcn_s_sleep(127);
-                if (++waited_passes > A.wait_passes) {
+                const uint64_t waited = lds_uniform(wsrv + SV_WAITED) + 1;
+                if (lane == 0) wsrv[SV_WAITED] = waited;
+                if (waited > A.wait_passes) {
                     // the host never published this far: report it and leave
-                    served_report(A, lane, kServedErrWait, ticket);
+                    served_report(A, lane, kServedErrWait, lds_uniform(wsrv + SV_TICKET));
                     queue_empty = true;
                 }
             }
-        } else if (SERVED && idle_from != 0) {
-            idle_ticks += (uint64_t)wall_clock64() - idle_from;
-            idle_from = 0;
+        } else if (SERVED && idle_stretch) {
+            idle_stretch = false;
+            if (lane == 0) wsrv[SV_IDLE_TICKS] += (uint64_t)wall_clock64() - wsrv[SV_IDLE_FROM];
         }
 
         // ---------------- one event step per live lane -----------------------
@@ -1036,14 +1067,27 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
             }
         }
     }
-    if (SERVED) {
+    if (SERVED && lane == 0) {
         const uint64_t now = wall_clock64();
-        if (idle_from != 0) idle_ticks += now - idle_from;
-        if (lane == 0) {
-            atomicAdd(&A.served->alive_ticks, (unsigned long long)(now - born));
-            atomicAdd(&A.served->idle_ticks, (unsigned long long)idle_ticks);
-        }
+        uint64_t idle = wsrv[SV_IDLE_TICKS];
+        if (idle_stretch) idle += now - wsrv[SV_IDLE_FROM];
+        atomicAdd(&A.served->alive_ticks, (unsigned long long)(now - wsrv[SV_BORN]));
+        atomicAdd(&A.served->idle_ticks, (unsigned long long)idle);
     }
+}
+
+// A batch launch: one kernel per kind of problem and precision.
+template <int G, int EST, int SRC, bool FP32, bool TRACE>
+__global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
+{
+    track_loop<G, EST, SRC, FP32, TRACE, false>(A);
+}
+
+// A served round: every kind of problem of one precision.
+template <bool FP32>
+__global__ void __launch_bounds__(512) served_kernel(TrackArgs A)
+{
+    track_loop<GEOM_ANY, -1, -1, FP32, false, true>(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -1115,10 +1159,9 @@ typedef void (*TrackFn)(TrackArgs);
 template <int G, int EST, int SRC>
 static TrackFn pick_prec(const Variant &v)
 {
-    if (v.fp32)
-        return v.trace ? track_kernel<G, EST, SRC, true, true, false> : track_kernel<G, EST, SRC, true, false, false>;
-    if (v.trace) return track_kernel<G, EST, SRC, false, true, false>;
-    return track_kernel<G, EST, SRC, false, false, false>;
+    if (v.fp32) return v.trace ? track_kernel<G, EST, SRC, true, true> : track_kernel<G, EST, SRC, true, false>;
+    if (v.trace) return track_kernel<G, EST, SRC, false, true>;
+    return track_kernel<G, EST, SRC, false, false>;
 }
 
 template <int G>
@@ -1134,8 +1177,7 @@ static TrackFn pick(const Variant &v)
     // served rounds: one kernel per precision for every kind of problem
     if (v.served) {
         if (v.trace || v.geom != GEOM_ANY) return nullptr;
-        return v.fp32 ? track_kernel<GEOM_ANY, -1, -1, true, false, true>
-                      : track_kernel<GEOM_ANY, -1, -1, false, false, true>;
+        return v.fp32 ? served_kernel<true> : served_kernel<false>;
     }
     switch (v.geom) {
     case GEOM_ROD: return pick_geom<GEOM_ROD>(v);
