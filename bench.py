@@ -524,10 +524,12 @@ def physical_cpu():
     return model, (len(cores) or None)
 
 
-def run_form(cls, torch, stream, perf_model, specs, steps, warmup, fp64_steps, label):
+def run_form(cls, torch, stream, perf_model, specs, steps, warmup, fp64_steps, label, tune=False):
     """One workload: `steps` timed batched FP32 launches (after `warmup`), then the
     plain FP64 one-problem-per-launch runs, the first of them on the seeds of the last
-    timed FP32 step (common random numbers: the acceptance rule of the FP32 form)."""
+    timed FP32 step (common random numbers: the acceptance rule of the FP32 form).
+    With `tune`, the FP32 launches use the autotuner's launch configuration for these
+    sets, and the default configuration is timed as well for comparison."""
     total_hist = sum(s.histories for s in specs)
     geom = specs[0].geom_name
     probs = [make_problem(cls, s, fp32=True) for s in specs]
@@ -535,9 +537,22 @@ def run_form(cls, torch, stream, perf_model, specs, steps, warmup, fp64_steps, l
         cls.cls_set_stream(p, stream)
     log(f"{label}: fp32 batched, {len(specs)} sets x {_span(s.histories for s in specs)} histories, "
         f"{warmup} warmup + {steps} steps")
+    tuning = None
     try:
+        if tune:
+            cls.cls_set_launch_config(0, 0, 0, 0)
+            d_steps = max(1, min(steps, 3))
+            d_wall, d_ms, _ = run_batch_steps(cls, torch, probs, specs, d_steps, 1, 1000)
+            t0 = time.perf_counter()
+            cfg, tuned_rate = cls.cls_autotune(probs, [s.histories for s in specs])
+            tuning = {"autotuned_config": cfg, "autotune_seconds": time.perf_counter() - t0,
+                      "default_config_value": total_hist * d_steps / d_wall,
+                      "default_config_kernel_ms": d_ms / d_steps, "default_config_steps": d_steps}
+            log(f"  autotuned {cfg} in {tuning['autotune_seconds']:.1f} s; default configuration "
+                f"{tuning['default_config_value']:.4g} hist/s ({d_steps} steps)")
         wall, track_ms, full32 = run_batch_steps(cls, torch, probs, specs, steps, warmup, 0)
     finally:
+        cls.cls_set_launch_config(0, 0, 0, 0)
         for p in probs:
             cls.cls_destroy_problem(p)
     tallies = [f[0] for f in full32]
@@ -553,6 +568,7 @@ def run_form(cls, torch, stream, perf_model, specs, steps, warmup, fp64_steps, l
     achieved = slots / (kernel_ms * 1e-3) / 1e12
     peak = perf_model.PEAK_SLOTS_PER_S / 1e12
     out = {"value": value, "unit": "histories/s", "ms_per_step": 1e3 * wall / steps, "kernel_ms": kernel_ms,
+           "launch_config": tuning if tuning else "default",
            "collisions_per_s": collisions * steps / wall, "flights_per_s": flights * steps / wall,
            "flights_per_history": flights / total_hist, "histories_per_step": total_hist,
            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
@@ -603,6 +619,9 @@ def main() -> int:
     ap.add_argument("--histories", type=int, default=0, help="override histories per set")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed passes of the FP64 plain leg (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="oracle sample budget (0 = skip)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: the main workload's FP32 launches use the autotuned configuration "
+                         "(the default configuration is timed as well); 0: default configuration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--cube3d-steps", type=int, default=3,
@@ -647,7 +666,7 @@ def main() -> int:
 
     # ---- the main workload: FP32 batched (timed steps) vs FP64 plain ----------
     main_leg, full32 = run_form(cls, torch, stream, perf_model, specs, args.steps, args.warmup, args.fp64_steps,
-                                args.workload)
+                                args.workload, tune=args.autotune)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -805,6 +824,7 @@ def main() -> int:
         "collisions_per_s": main_leg["collisions_per_s"],
         "flights_per_s": main_leg["flights_per_s"],
         "flights_per_history": main_leg["flights_per_history"],
+        "launch_config": main_leg["launch_config"],
         "fp64_plain": main_leg.get("fp64_plain"),
         "speedup_vs_fp64_plain": main_leg.get("speedup_vs_fp64_plain"),
         "fp32_vs_fp64_same_streams": main_leg.get("fp32_vs_fp64_same_streams"),

@@ -218,22 +218,30 @@ void cls_batch_destroy(cls_batch *b);
  *   max_chunk        largest number of histories per work chunk (>= 64; default
  *                    16384); a chunk is also one batch of the flux error;
  *   refill_min       idle lanes a wave waits for before it hands out new
- *                    histories (1..64; default 4; 1 refills every step).
+ *                    histories (1..64; default 4; 1 refills every step);
+ *   slots            LDS tally buffers per wave, 1 or 2 (automatic: two, or one
+ *                    when it keeps more waves resident and at most a fifth of
+ *                    the histories are in chunks below 2048); a choice that
+ *                    does not fit the LDS falls back to one.
  * Values out of range give CLS_ERR_INVALID_ARG. */
 typedef struct {
     int waves_per_block;
     int blocks_per_cu;
     int max_chunk;
     int refill_min;
+    int slots;
 } cls_launch_config;
 cls_status cls_set_launch_config(const cls_launch_config *cfg);
 cls_status cls_get_launch_config(cls_launch_config *cfg);
 
-/* Autotuner: time candidate launch shapes (workgroup size, chunk size, refill
- * threshold) on a calibration part of about sample_histories histories (0: a
+/* Autotuner: time candidate launch shapes on a calibration part of about
+ * sample_histories histories (0: a
  * quarter of the summed histories, at least 2e7) of the batch cls_run_batch
  * would run for `problems` and `histories` (same rules): the first chunks of
- * every problem, cut as in the whole batch. Makes the fastest shape the
+ * every problem, cut as in the whole batch. The search runs in two stages:
+ * LDS tally buffers per wave (automatic, 1, 2) x workgroup size (automatic, 2,
+ * 4, 8 waves), then, for the fastest, chunk size (4096, 16384, 65536; the chunk
+ * is also the error batch) x refill threshold (1, 4, 16). Makes the fastest shape the
  * process-wide launch configuration and returns it
  * in *best (and its rate in histories/s in *best_rate, 0 when it came from the
  * cache). When the environment variable CLS_AUTOTUNE_CACHE names a file,

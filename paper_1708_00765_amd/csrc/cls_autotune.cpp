@@ -1,9 +1,11 @@
-// Launch-shape autotuner. Candidate shapes -- workgroup size, persistent
-// workgroups per compute unit, histories per chunk and the idle-lane refill
-// threshold ("regroup cadence") -- are timed on a calibration sample of the
-// caller's problems run as one batched launch; the fastest becomes the
-// process-wide launch configuration. Results are cached in a text file (one
-// line per key: device, kernel variant and flux-mesh size class) named by the
+// Launch-shape autotuner. Candidate shapes are timed on a calibration sample
+// of the caller's problems run as one batched launch, in two stages: the LDS
+// tally buffers per wave (one or two, or the automatic choice) with the
+// workgroup size, then, for the fastest of those, the histories per chunk
+// (which is also the error batch) with the idle-lane refill threshold. The
+// fastest becomes the process-wide launch configuration. Results are cached in
+// a text file (one line per key: device, kernel variant and flux-mesh size
+// class, then the five fields of cls_launch_config) named by the
 // CLS_AUTOTUNE_CACHE environment variable, when it is set.
 #include <hip/hip_runtime.h>
 
@@ -40,9 +42,11 @@ bool cache_lookup(const std::string &key, cls_launch_config *cfg)
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
         char k[160];
-        cls_launch_config c;
-        if (std::sscanf(line, "%159s %d %d %d %d", k, &c.waves_per_block, &c.blocks_per_cu, &c.max_chunk,
-                        &c.refill_min) == 5 && key == k) {
+        cls_launch_config c = {0, 0, 0, 0, 0};
+        // four fields (without the buffer count, read as automatic) or five
+        const int got = std::sscanf(line, "%159s %d %d %d %d %d", k, &c.waves_per_block, &c.blocks_per_cu,
+                                    &c.max_chunk, &c.refill_min, &c.slots);
+        if (got >= 5 && key == k) {
             *cfg = c;       // the last line for a key wins
             found = true;
         }
@@ -57,7 +61,8 @@ void cache_store(const std::string &key, const cls_launch_config &c)
     if (!path || !*path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), c.waves_per_block, c.blocks_per_cu, c.max_chunk, c.refill_min);
+    std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), c.waves_per_block, c.blocks_per_cu, c.max_chunk, c.refill_min,
+                 c.slots);
     std::fclose(f);
 }
 
@@ -89,35 +94,51 @@ extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t 
     cls_launch_config saved;
     cls_status st = cls_get_launch_config(&saved);
     if (st != CLS_OK) return st;
-    const int waves[] = {0, 2, 4, 8};
-    const int chunks[] = {4096, 16384, 65536};
-    const int refills[] = {1, 4, 16};
     double best_r = -1.0;
     cls_launch_config best_c = saved;
-    for (int w : waves)
-        for (int c : chunks)
-            for (int r : refills) {
-                cls_launch_config cfg = {w, 0, c, r};
-                st = cls_set_launch_config(&cfg);
-                if (st != CLS_OK) return st;
-                double ms = 1e30;
-                uint64_t processed = 0;
-                for (int rep = 0; rep < 2; ++rep) {
-                    st = run_batch_part(problems, histories, seeds.data(), n, fraction, &processed);
-                    if (st != CLS_OK && st != CLS_ERR_EVENT_CAP) {
-                        (void)cls_set_launch_config(&saved);
-                        return st;
-                    }
-                    cls_tallies t;
-                    (void)cls_read_tallies(problems[0], &t, nullptr, nullptr, 0);
-                    ms = std::min(ms, t.track_ms);
-                }
-                const double rate = (double)processed / (ms * 1e-3);
-                if (rate > best_r) {
-                    best_r = rate;
-                    best_c = cfg;
-                }
+    // one candidate: two timed runs of the calibration part, the faster kept
+    auto try_cfg = [&](const cls_launch_config &cfg) -> cls_status {
+        cls_status r = cls_set_launch_config(&cfg);
+        if (r != CLS_OK) return r;
+        double ms = 1e30;
+        uint64_t processed = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+            r = run_batch_part(problems, histories, seeds.data(), n, fraction, &processed);
+            if (r != CLS_OK && r != CLS_ERR_EVENT_CAP) return r;
+            cls_tallies t;
+            (void)cls_read_tallies(problems[0], &t, nullptr, nullptr, 0);
+            ms = std::min(ms, t.track_ms);
+        }
+        const double rate = (double)processed / (ms * 1e-3);
+        if (rate > best_r) {
+            best_r = rate;
+            best_c = cfg;
+        }
+        return CLS_OK;
+    };
+    // stage 1: LDS buffers per wave x workgroup size, default chunk and refill
+    const int slot_choices[] = {0, 1, 2};
+    const int waves[] = {0, 2, 4, 8};
+    for (int sl : slot_choices)
+        for (int w : waves) {
+            st = try_cfg({w, 0, 0, 0, sl});
+            if (st != CLS_OK) {
+                (void)cls_set_launch_config(&saved);
+                return st;
             }
+        }
+    // stage 2: chunk size x refill threshold for the stage-1 winner
+    const cls_launch_config shape = best_c;
+    const int chunks[] = {4096, 16384, 65536};
+    const int refills[] = {1, 4, 16};
+    for (int c : chunks)
+        for (int r : refills) {
+            st = try_cfg({shape.waves_per_block, 0, c, r, shape.slots});
+            if (st != CLS_OK) {
+                (void)cls_set_launch_config(&saved);
+                return st;
+            }
+        }
     *best = best_c;
     if (best_rate) *best_rate = best_r;
     cache_store(key, best_c);

@@ -330,6 +330,8 @@ cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *
     int best_waves = 0, best_bpc = 0, best_slots = 2;
     const int candidates[4] = {4, 8, 2, 1};
     for (int slots = 2; slots >= 1; --slots) {
+        // a requested buffer count is the only one tried
+        if (s.slots_request != 0 && slots != s.slots_request) continue;
         const size_t pw = wave_bytes(slots);
         for (int c : candidates) {
             if (s.waves_per_block > 0 && c != s.waves_per_block) continue;
@@ -339,7 +341,7 @@ cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *
                 const hipError_t e = occupancy_cached(v, di.id, c * 64, pw * (size_t)c, &bpc);
                 if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
             }
-            if (slots == 1) {
+            if (slots == 1 && s.slots_request == 0) {
                 const uint64_t waves_total = (uint64_t)di.cus * (uint64_t)std::max(bpc, 1) * (uint64_t)c;
                 if (!small_share || small_share(waves_total, (uint64_t)s.max_chunk) > kSingleSlotMaxSmallShare)
                     continue;
@@ -515,11 +517,13 @@ cls_status cls_set_launch_config(const cls_launch_config *cfg)
     if (cfg->waves_per_block != 0 && cfg->waves_per_block != 1 && cfg->waves_per_block != 2 &&
         cfg->waves_per_block != 4 && cfg->waves_per_block != 8)
         return fail(CLS_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
+    if (cfg->slots < 0 || cfg->slots > 2) return fail(CLS_ERR_INVALID_ARG, "slots must be 0, 1 or 2");
     std::lock_guard<std::mutex> lk(g_mu);
     g_shape.waves_per_block = cfg->waves_per_block;
     g_shape.blocks_per_cu = cfg->blocks_per_cu;
     g_shape.max_chunk = cfg->max_chunk;
     g_shape.refill_min = cfg->refill_min;
+    g_shape.slots_request = cfg->slots;
     return CLS_OK;
 }
 
@@ -531,6 +535,7 @@ cls_status cls_get_launch_config(cls_launch_config *cfg)
     cfg->blocks_per_cu = s.blocks_per_cu;
     cfg->max_chunk = s.max_chunk;
     cfg->refill_min = s.refill_min;
+    cfg->slots = s.slots_request;
     return CLS_OK;
 }
 

@@ -164,7 +164,8 @@ struct LaunchShape {
     int blocks_per_cu;
     int max_chunk;
     int refill_min;
-    int slots = 2;               // chosen by the launch sizing, not by the caller
+    int slots = 2;               // chosen by the launch sizing
+    int slots_request = 0;       // the caller's choice (0: automatic, 1 or 2)
 };
 
 // Kernel variants: geometry x estimator x source x precision x trace, and

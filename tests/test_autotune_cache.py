@@ -1,0 +1,92 @@
+"""The autotuner's result cache, without a GPU: the key of a batch (kernel
+variant and flux-mesh size class), the last line for a key winning, the
+four-field lines of older caches, and a cached configuration becoming the
+process-wide launch configuration before any device work."""
+from __future__ import annotations
+
+import pytest
+
+
+@pytest.fixture(scope="module")
+def cls():
+    from paper_1708_00765_amd import cls as mod
+    yield mod
+    mod.cls_set_launch_config(0, 0, 0, 0)
+
+
+def _problem(cls, d=3, nbins=100, flags=0, source=0):
+    return cls.cls_create_problem(d, 10.0, (0.5, 1.0), (0.2, 0.9), (1.0, 0.3), source=source, nbins=nbins,
+                                  flags=flags)
+
+
+def _tuned(cls, monkeypatch, path, lines, **problem):
+    path.write_text("".join(l + "\n" for l in lines))
+    monkeypatch.setenv("CLS_AUTOTUNE_CACHE", str(path))
+    p = _problem(cls, **problem)
+    try:
+        cfg, rate = cls.cls_autotune([p], [1000])
+    finally:
+        cls.cls_destroy_problem(p)
+    return cfg, rate
+
+
+def test_cached_configuration_is_used(cls, monkeypatch, tmp_path):
+    lines = ["gfx950/g3/e1/s0/fp32/k128 4 0 16384 8 2"]
+    cfg, rate = _tuned(cls, monkeypatch, tmp_path / "c.txt", lines, d=3, nbins=100, flags=cls.CLS_F_FP32)
+    assert cfg == {"waves_per_block": 4, "blocks_per_cu": 0, "max_chunk": 16384, "refill_min": 8, "slots": 2}
+    assert rate == 0.0
+    assert cls.cls_get_launch_config() == cfg      # the process-wide configuration now
+    cls.cls_set_launch_config(0, 0, 0, 0)
+
+
+@pytest.mark.parametrize("nbins,cls_k", [(1, 64), (64, 64), (65, 128), (128, 128), (129, 256), (1000, 1024),
+                                         (2048, 2048)])
+def test_mesh_size_class(cls, monkeypatch, tmp_path, nbins, cls_k):
+    lines = [f"gfx950/g3/e1/s0/fp32/k{k} {w} 0 4096 4 1" for k, w in ((64, 1), (128, 2), (256, 4), (1024, 8),
+                                                                       (2048, 2))]
+    want = {64: 1, 128: 2, 256: 4, 1024: 8, 2048: 2}[cls_k]
+    cfg, _ = _tuned(cls, monkeypatch, tmp_path / "c.txt", lines, d=3, nbins=nbins, flags=cls.CLS_F_FP32)
+    assert cfg["waves_per_block"] == want
+    cls.cls_set_launch_config(0, 0, 0, 0)
+
+
+def test_variant_fields_of_the_key(cls, monkeypatch, tmp_path):
+    """Geometry (rod 0, slab 1, extruded 2, cube 3), estimator (collision 0,
+    track length 1), source (face 0, volume 1) and precision each select their
+    own line."""
+    lines = ["gfx950/g0/e0/s0/fp64/k128 1 0 4096 4 0",
+             "gfx950/g1/e1/s0/fp64/k128 2 0 4096 4 0",
+             "gfx950/g2/e1/s1/fp32/k128 4 0 4096 4 0",
+             "gfx950/g3/e0/s0/fp32/k128 8 0 4096 4 0",
+             "gfx950/g3/e1/s0/fp64/k128 1 0 65536 4 0"]
+    cases = [(dict(d=1, flags=cls.CLS_F_COLLISION_FLUX), 1),
+             (dict(d=1, flags=cls.CLS_F_D1_SLAB), 2),
+             (dict(d=2, flags=cls.CLS_F_FP32, source=1), 4),
+             (dict(d=3, flags=cls.CLS_F_FP32 | cls.CLS_F_COLLISION_FLUX), 8),
+             (dict(d=3, flags=0), 1)]
+    for kw, want in cases:
+        cfg, _ = _tuned(cls, monkeypatch, tmp_path / "c.txt", lines, nbins=100, **kw)
+        assert cfg["waves_per_block"] == want, kw
+    cls.cls_set_launch_config(0, 0, 0, 0)
+
+
+def test_last_line_wins_and_old_lines_read(cls, monkeypatch, tmp_path):
+    lines = ["gfx950/g3/e1/s0/fp32/k128 2 0 4096 4 1",
+             "gfx950/g3/e1/s0/fp32/k128 8 0 65536 16",      # four fields: automatic buffer count
+             "gfx950/g2/e1/s0/fp32/k128 1 0 4096 4 2"]
+    cfg, _ = _tuned(cls, monkeypatch, tmp_path / "c.txt", lines, d=3, nbins=100, flags=cls.CLS_F_FP32)
+    assert cfg == {"waves_per_block": 8, "blocks_per_cu": 0, "max_chunk": 65536, "refill_min": 16, "slots": 0}
+    cls.cls_set_launch_config(0, 0, 0, 0)
+
+
+def test_uncached_variant_needs_the_device(cls, monkeypatch, tmp_path):
+    """A batch whose key is not in the cache is calibrated on the GPU; without
+    one the call fails with a status (and the launch configuration stays)."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present: the calibration would run")
+    before = cls.cls_get_launch_config()
+    with pytest.raises(cls.ClsError):
+        _tuned(cls, monkeypatch, tmp_path / "c.txt", ["gfx950/g3/e1/s0/fp32/k128 2 0 4096 4 1"],
+               d=3, nbins=300, flags=cls.CLS_F_FP32)
+    assert cls.cls_get_launch_config() == before

@@ -96,9 +96,11 @@ def test_launch_config_validation(cls):
         cls.cls_set_launch_config(waves_per_block=3)
     with pytest.raises(cls.ClsError):
         cls.cls_set_launch_config(refill_min=65)
-    cls.cls_set_launch_config(2, 4, 1024, 8)
+    with pytest.raises(cls.ClsError):
+        cls.cls_set_launch_config(slots=3)
+    cls.cls_set_launch_config(2, 4, 1024, 8, 1)
     assert cls.cls_get_launch_config() == {"waves_per_block": 2, "blocks_per_cu": 4, "max_chunk": 1024,
-                                           "refill_min": 8}
+                                           "refill_min": 8, "slots": 1}
     cls.cls_set_launch_config(0, 0, 0, 0)
     assert cls.cls_get_launch_config() == old
 

@@ -173,7 +173,8 @@ def test_results_do_not_depend_on_launch_shape_and_autotune(cls, fp32):
     """Counts exactly, score and flux sums to FP64 summation order, for launch
     shapes from one-wave workgroups with 64-history chunks refilled lane by
     lane (a lane changes chunk slot after almost every history) to 65536-history
-    chunks; then the autotuner's choice (FP32)."""
+    chunks, with one or two LDS tally buffers per wave forced; then the
+    autotuner's choice (FP32)."""
     specs = workload("cube3d_track", histories=300_000)[:4]
     probs = [gpu_problem(s, fp32=fp32) for s in specs]
     hist = [s.histories for s in specs]
@@ -181,7 +182,8 @@ def test_results_do_not_depend_on_launch_shape_and_autotune(cls, fp32):
     try:
         cls.cls_run_batch(probs, hist, seeds)
         base = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(probs, specs)]
-        for cfg in ((1, 1, 64, 1), (8, 0, 1024, 16), (2, 3, 65536, 4)):
+        for cfg in ((1, 1, 64, 1, 0), (8, 0, 1024, 16, 0), (2, 3, 65536, 4, 0), (0, 0, 4096, 4, 1),
+                    (0, 0, 4096, 4, 2)):
             cls.cls_set_launch_config(*cfg)
             cls.cls_run_batch(probs, hist, seeds)
             for s, p, (t0, f0, _) in zip(specs, probs, base):
