@@ -524,7 +524,7 @@ def physical_cpu():
     return model, (len(cores) or None)
 
 
-def run_form(cls, torch, stream, perf_model, specs, steps, warmup, fp64_steps, label, tune=False):
+def run_form(cls, torch, stream, perf_model, specs, steps, warmup, fp64_steps, label, tune=False, max_chunk=0):
     """One workload: `steps` timed batched FP32 launches (after `warmup`), then the
     plain FP64 one-problem-per-launch runs, the first of them on the seeds of the last
     timed FP32 step (common random numbers: the acceptance rule of the FP32 form).
@@ -539,7 +539,10 @@ def run_form(cls, torch, stream, perf_model, specs, steps, warmup, fp64_steps, l
         f"{warmup} warmup + {steps} steps")
     tuning = None
     try:
-        if tune:
+        if max_chunk > 0:
+            cls.cls_set_launch_config(0, 0, max_chunk, 0)
+            tuning = {"max_chunk": max_chunk}
+        elif tune:
             cls.cls_set_launch_config(0, 0, 0, 0)
             d_steps = max(1, min(steps, 3))
             d_wall, d_ms, _ = run_batch_steps(cls, torch, probs, specs, d_steps, 1, 1000)
@@ -619,6 +622,9 @@ def main() -> int:
     ap.add_argument("--histories", type=int, default=0, help="override histories per set")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed passes of the FP64 plain leg (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="oracle sample budget (0 = skip)")
+    ap.add_argument("--max-chunk", type=int, default=0,
+                    help="histories per work chunk (= error batch) of the main workload's FP32 launches "
+                         "(0: the launch configuration's; implies --autotune 0)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: the main workload's FP32 launches use the autotuned configuration "
                          "(the default configuration is timed as well); 0: default configuration")
@@ -666,7 +672,8 @@ def main() -> int:
 
     # ---- the main workload: FP32 batched (timed steps) vs FP64 plain ----------
     main_leg, full32 = run_form(cls, torch, stream, perf_model, specs, args.steps, args.warmup, args.fp64_steps,
-                                args.workload, tune=args.autotune)
+                                args.workload, tune=bool(args.autotune) and args.max_chunk <= 0,
+                                max_chunk=args.max_chunk)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")

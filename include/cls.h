@@ -216,13 +216,23 @@ void cls_batch_destroy(cls_batch *b);
  *   blocks_per_cu    persistent workgroups per compute unit (automatic: as many as
  *                    are resident at once);
  *   max_chunk        largest number of histories per work chunk (>= 64; default
- *                    16384); a chunk is also one batch of the flux error;
+ *                    16384);
  *   refill_min       idle lanes a wave waits for before it hands out new
  *                    histories (1..64; default 4; 1 refills every step);
  *   slots            LDS tally buffers per wave, 1 or 2 (automatic: two, or one
  *                    when it keeps more waves resident and at most a fifth of
  *                    the histories are in chunks below 2048); a choice that
- *                    does not fit the LDS falls back to one.
+ *                    does not fit the LDS falls back to one;
+ *   chunk_batches    1: every chunk is one batch of the per-bin flux error;
+ *                    0 (default): in runs and batches (not served requests) a
+ *                    wave gathers the chunks it takes of one problem into one
+ *                    batch of up to max(chunk, n / 256) of the problem's n
+ *                    histories, so that a problem keeps at least 256 batches
+ *                    when its chunks allow and the flush traffic falls with the
+ *                    batch count. Which histories share a batch then depends on
+ *                    the order in which waves take chunks, so the batch count
+ *                    and the per-bin flux errors (not the counts, the means or
+ *                    the per-history errors) vary from run to run.
  * Values out of range give CLS_ERR_INVALID_ARG. */
 typedef struct {
     int waves_per_block;
@@ -230,6 +240,7 @@ typedef struct {
     int max_chunk;
     int refill_min;
     int slots;
+    int chunk_batches;
 } cls_launch_config;
 cls_status cls_set_launch_config(const cls_launch_config *cfg);
 cls_status cls_get_launch_config(cls_launch_config *cfg);
@@ -339,7 +350,7 @@ void cls_server_destroy(cls_server *s);
  * Runs `histories` histories of p with stream key `seed` exactly as
  * cls_run_async would (same launch shape, chunks and kernels; integer tallies
  * bitwise equal, FP64 sums up to the order of additions), but allocates
- * nothing: the run's device workspace is a static 48 KB array that the library
+ * nothing: the run's device workspace is a static 64 KB array that the library
  * holds on each device it runs on until the process ends, and nothing is
  * copied to the host.
  *   p            a problem from cls_create_problem (only read; CLS_F_TRACE is

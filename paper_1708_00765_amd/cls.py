@@ -80,7 +80,8 @@ class cls_quenched_tallies(ctypes.Structure):
 
 class cls_launch_config(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int), ("blocks_per_cu", ctypes.c_int),
-                ("max_chunk", ctypes.c_int), ("refill_min", ctypes.c_int), ("slots", ctypes.c_int)]
+                ("max_chunk", ctypes.c_int), ("refill_min", ctypes.c_int), ("slots", ctypes.c_int),
+                ("chunk_batches", ctypes.c_int)]
 
 
 class cls_server_config(ctypes.Structure):
@@ -248,14 +249,17 @@ def cls_run_batch(problems, histories, seeds, allow_cap: bool = False) -> int:
     return _check(_lib.cls_run_batch(arr, hs, ss, n), "cls_run_batch", allow)
 
 
-def cls_set_launch_config(waves_per_block=0, blocks_per_cu=0, max_chunk=0, refill_min=0, slots=0) -> None:
-    cfg = cls_launch_config(int(waves_per_block), int(blocks_per_cu), int(max_chunk), int(refill_min), int(slots))
+def cls_set_launch_config(waves_per_block=0, blocks_per_cu=0, max_chunk=0, refill_min=0, slots=0,
+                          chunk_batches=0) -> None:
+    cfg = cls_launch_config(int(waves_per_block), int(blocks_per_cu), int(max_chunk), int(refill_min), int(slots),
+                            int(chunk_batches))
     _check(_lib.cls_set_launch_config(ctypes.byref(cfg)), "cls_set_launch_config")
 
 
 def _cfg_dict(cfg) -> dict:
     return {"waves_per_block": cfg.waves_per_block, "blocks_per_cu": cfg.blocks_per_cu,
-            "max_chunk": cfg.max_chunk, "refill_min": cfg.refill_min, "slots": cfg.slots}
+            "max_chunk": cfg.max_chunk, "refill_min": cfg.refill_min, "slots": cfg.slots,
+            "chunk_batches": cfg.chunk_batches}
 
 
 def cls_get_launch_config() -> dict:

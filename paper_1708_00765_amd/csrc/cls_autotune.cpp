@@ -2,11 +2,12 @@
 // of the caller's problems run as one batched launch, in two stages: the LDS
 // tally buffers per wave (one or two, or the automatic choice) with the
 // workgroup size, then, for the fastest of those, the histories per chunk
-// (which is also the error batch) with the idle-lane refill threshold. The
-// fastest becomes the process-wide launch configuration. Results are cached in
-// a text file (one line per key: device, kernel variant and flux-mesh size
-// class, then the five fields of cls_launch_config) named by the
-// CLS_AUTOTUNE_CACHE environment variable, when it is set.
+// with the idle-lane refill threshold. The fastest becomes the process-wide
+// launch configuration (chunk_batches, not a performance choice, stays as the
+// caller set it). Results are cached in a text file (one line per key: device,
+// kernel variant and flux-mesh size class, then the first five fields of
+// cls_launch_config) named by the CLS_AUTOTUNE_CACHE environment variable,
+// when it is set.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,11 +43,12 @@ bool cache_lookup(const std::string &key, cls_launch_config *cfg)
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
         char k[160];
-        cls_launch_config c = {0, 0, 0, 0, 0};
+        cls_launch_config c = {0, 0, 0, 0, 0, 0};
         // four fields (without the buffer count, read as automatic) or five
         const int got = std::sscanf(line, "%159s %d %d %d %d %d", k, &c.waves_per_block, &c.blocks_per_cu,
                                     &c.max_chunk, &c.refill_min, &c.slots);
         if (got >= 5 && key == k) {
+            c.chunk_batches = cfg->chunk_batches;
             *cfg = c;       // the last line for a key wins
             found = true;
         }
@@ -78,6 +80,10 @@ extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t 
     int max_bins = 1;
     for (int i = 0; i < n; ++i) max_bins = std::max(max_bins, problems[i]->nbins);
     const std::string key = cache_key(variant_of(problems[0]), max_bins);
+    cls_launch_config saved;
+    cls_status st = cls_get_launch_config(&saved);
+    if (st != CLS_OK) return st;
+    *best = saved;
     if (cache_lookup(key, best)) {
         if (best_rate) *best_rate = 0.0;
         return cls_set_launch_config(best);
@@ -91,9 +97,6 @@ extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t 
     const double fraction = std::min(1.0, (double)sample_histories / (double)total);
     std::vector<uint64_t> seeds(n);
     for (int i = 0; i < n; ++i) seeds[i] = 0x5DEECE66Dull * (uint64_t)(i + 1);
-    cls_launch_config saved;
-    cls_status st = cls_get_launch_config(&saved);
-    if (st != CLS_OK) return st;
     double best_r = -1.0;
     cls_launch_config best_c = saved;
     // one candidate: two timed runs of the calibration part, the faster kept
@@ -121,7 +124,7 @@ extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t 
     const int waves[] = {0, 2, 4, 8};
     for (int sl : slot_choices)
         for (int w : waves) {
-            st = try_cfg({w, 0, 0, 0, sl});
+            st = try_cfg({w, 0, 0, 0, sl, saved.chunk_batches});
             if (st != CLS_OK) {
                 (void)cls_set_launch_config(&saved);
                 return st;
@@ -133,7 +136,7 @@ extern "C" cls_status cls_autotune(cls_problem *const *problems, const uint64_t 
     const int refills[] = {1, 4, 16};
     for (int c : chunks)
         for (int r : refills) {
-            st = try_cfg({shape.waves_per_block, 0, c, r, shape.slots});
+            st = try_cfg({shape.waves_per_block, 0, c, r, shape.slots, saved.chunk_batches});
             if (st != CLS_OK) {
                 (void)cls_set_launch_config(&saved);
                 return st;

@@ -110,7 +110,7 @@ size_t workspace_bytes(int nbins, uint64_t trace_n)
     b += align256(sizeof(DevProblem));
     b += align256(4 * sizeof(uint64_t));
     b += align256(C_COUNT * sizeof(uint64_t));
-    b += align256((2 + 2 * (size_t)nbins) * sizeof(double));
+    b += align256(sums_words(nbins) * sizeof(double));
     b += align256(record_words(nbins) * sizeof(uint64_t));
     b += align256((size_t)trace_n * sizeof(uint64_t));
     b += align256((size_t)trace_n * sizeof(uint32_t));
@@ -123,7 +123,7 @@ static void carve(cls_problem *p, size_t trace_n)
     p->d_prob = (DevProblem *)q; q += align256(sizeof(DevProblem));
     p->d_items = (uint64_t *)q; q += align256(4 * sizeof(uint64_t));
     p->d_counters = (uint64_t *)q; q += align256(C_COUNT * sizeof(uint64_t));
-    p->d_sums = (double *)q; q += align256((2 + 2 * (size_t)p->nbins) * sizeof(double));
+    p->d_sums = (double *)q; q += align256(sums_words(p->nbins) * sizeof(double));
     p->d_record = (uint64_t *)q; q += align256(record_words(p->nbins) * sizeof(uint64_t));
     p->d_trace_hash = trace_n ? (uint64_t *)q : nullptr; q += align256(trace_n * sizeof(uint64_t));
     p->d_trace_len = trace_n ? (uint32_t *)q : nullptr;
@@ -192,6 +192,11 @@ uint32_t unit_threshold(double q)
     return 0x3F800000u + (uint32_t)t;
 }
 
+uint32_t batch_limit(uint64_t histories, uint64_t chunk, const LaunchShape &s)
+{
+    return (uint32_t)(s.chunk_batches == 1 ? chunk : sched::batch_histories(histories, chunk));
+}
+
 void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,
                              uint64_t trace_n, DevProblem *out)
 {
@@ -227,7 +232,7 @@ void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, u
     out->max_steps = sched::flight_cap(chunk);
     out->nbins = p->nbins;
     out->kind = problem_kind(p->geom, p->est, p->src);
-    out->kind_pad = 0;
+    out->batch_max = (uint32_t)chunk;
     out->counters = p->d_counters;
     out->sums = p->d_sums;
     out->record = p->d_record;
@@ -518,12 +523,15 @@ cls_status cls_set_launch_config(const cls_launch_config *cfg)
         cfg->waves_per_block != 4 && cfg->waves_per_block != 8)
         return fail(CLS_ERR_INVALID_ARG, "waves_per_block must be 0, 1, 2, 4 or 8");
     if (cfg->slots < 0 || cfg->slots > 2) return fail(CLS_ERR_INVALID_ARG, "slots must be 0, 1 or 2");
+    if (cfg->chunk_batches < 0 || cfg->chunk_batches > 1)
+        return fail(CLS_ERR_INVALID_ARG, "chunk_batches must be 0 or 1");
     std::lock_guard<std::mutex> lk(g_mu);
     g_shape.waves_per_block = cfg->waves_per_block;
     g_shape.blocks_per_cu = cfg->blocks_per_cu;
     g_shape.max_chunk = cfg->max_chunk;
     g_shape.refill_min = cfg->refill_min;
     g_shape.slots_request = cfg->slots;
+    g_shape.chunk_batches = cfg->chunk_batches;
     return CLS_OK;
 }
 
@@ -536,6 +544,7 @@ cls_status cls_get_launch_config(cls_launch_config *cfg)
     cfg->max_chunk = s.max_chunk;
     cfg->refill_min = s.refill_min;
     cfg->slots = s.slots_request;
+    cfg->chunk_batches = s.chunk_batches;
     return CLS_OK;
 }
 
@@ -564,6 +573,7 @@ cls_status cls_run_async(cls_problem *p, uint64_t histories, uint64_t seed)
     const uint64_t chunk = chunk_size(histories, waves_total, (uint64_t)used.max_chunk);
     const uint64_t n_items = (histories + chunk - 1) / chunk;
     fill_dev_problem(p, histories, seed, chunk, trace_n, p->h_prob);
+    p->h_prob->batch_max = batch_limit(histories, chunk, used);
     p->h_items[0] = 0;
     p->h_items[1] = n_items;
     p->h_items[2] = 0;
@@ -794,6 +804,7 @@ cls_status run_batch_part(cls_problem *const *problems, const uint64_t *historie
         const uint64_t tn = fraction >= 1.0 ? trace_count(p, histories[i]) : 0;
         const uint64_t chunk = batch_chunk_size(histories[i], total_hist, waves_total, (uint64_t)used.max_chunk);
         fill_dev_problem(p, histories[i], seeds[i], chunk, tn, &h_probs[i]);
+        h_probs[i].batch_max = batch_limit(histories[i], chunk, used);
         h_probs[i].record = d_rec + off;
         off += record_words(p->nbins);
         const uint64_t items = (histories[i] + chunk - 1) / chunk;

@@ -165,6 +165,7 @@ cls_status cls_batch_run(cls_batch *b, const uint64_t *histories, const uint64_t
         cls_problem *p = b->probs[i];
         const uint64_t chunk = batch_chunk_size(histories[i], total, b->waves_total, b->max_chunk);
         fill_dev_problem(p, histories[i], seeds[i], chunk, 0, &h_probs[i]);
+        h_probs[i].batch_max = batch_limit(histories[i], chunk, current_shape());
         h_probs[i].record = d_rec + off;
         off += record_words(p->nbins);
         h_items[i + 1] = h_items[i] + (histories[i] + chunk - 1) / chunk;

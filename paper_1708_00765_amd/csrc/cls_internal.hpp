@@ -31,6 +31,7 @@ enum Counter : int {
     C_HISTORIES = 0, C_TRANSMITTED, C_REFLECTED, C_ABSORBED, C_CAPPED,
     C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_INTERFACES, C_LATERAL, C_BATCHES,
     C_DONE_CHUNKS,              // chunks flushed (in-kernel finalize of served requests)
+    C_QUEUE_HEAD,               // chunks of the problem handed out in a batch launch (its work queue)
     C_COUNT = 16
 };
 
@@ -43,6 +44,12 @@ enum Result : int {
 };
 
 inline size_t record_words(int nbins) { return (size_t)C_COUNT + R_HEADER + 2 * (size_t)nbins; }
+
+// Sums of a problem (doubles): [0] the history score sum, [1] its square sum;
+// over the batches b of the flux error (n_b histories, per-bin sums s_b):
+// [2, 2 + K) S_k = sum s_b, [2 + K, 2 + 2K) P_k = sum s_b^2,
+// [2 + 2K, 2 + 3K) R_k = sum n_b s_b, and [2 + 3K] M = sum n_b^2.
+__host__ __device__ constexpr size_t sums_words(int nbins) { return 3 + 3 * (size_t)nbins; }
 
 // Per-problem parameters and output pointers, one record per problem of a
 // launch (device memory, or pinned host memory for a served round's table).
@@ -70,16 +77,20 @@ struct alignas(128) DevProblem {
     int32_t trace_bins;         // trace hash includes the bin of each event (else events and materials only)
     uint64_t seed;
     uint64_t histories;
-    uint64_t chunk;             // histories per work item (batch)
+    uint64_t chunk;             // histories per work item
     uint64_t chunk_base;        // chunk index of this launch's first work item of the problem
     uint64_t trace_n;           // histories with a recorded trace
     uint64_t max_steps;         // flight cap per history
     int32_t nbins;
     float dxf;                  // FP32 copy of dx
     int32_t kind;               // problem_kind(geometry, estimator, source)
-    int32_t kind_pad;
+    // Histories one wave may gather into one batch of the flux error: in a
+    // batch launch a wave adds the next chunk of the same problem to the batch
+    // it is filling while the sum stays within batch_max (batch_max == chunk:
+    // every chunk is a batch of its own, as in served rounds).
+    uint32_t batch_max;
     uint64_t *counters;         // C_COUNT u64
-    double *sums;               // [0] score sum, [1] score square sum, [2..2+K) S_k, [2+K..2+2K) Q_k
+    double *sums;               // sums_words(K) doubles
     uint64_t *record;           // finalize output, record_words(K) words
     uint64_t *trace_hash;
     uint32_t *trace_len;
@@ -135,7 +146,7 @@ struct ServedDev {
 struct TrackArgs {
     const DevProblem *probs;
     const uint64_t *item_start;  // nprobs + 1 prefix sums of work items
-    uint64_t *queue_head;        // work-item counter (zeroed before the launch)
+    uint64_t *queue_head;        // unused by batch launches (each problem's C_QUEUE_HEAD counts its chunks)
     int nprobs;
     int lds_stride;              // doubles per tally buffer (>= max nbins + 1, even)
     int refill_min;              // idle lanes a wave waits for before handing out histories
@@ -150,14 +161,14 @@ struct TrackArgs {
 };
 
 // LDS per wave beyond its one or two tally buffers: score sums of two slots
-// (4 doubles) and kSlotCounters 32-bit counters per slot (8 doubles).
+// (4 doubles) and kSlotCounters 64-bit counters per slot (16 doubles).
 constexpr int kSlotCounters = 8;
 // ... then the per-material flight parameters of the problem each slot holds:
 // 2 slots x 2 materials x 4 values, room for FP64 values.
 constexpr int kMatTableDoubles = 16;
 // ... then, in served rounds, the wave's claim state (see the kernel).
 constexpr int kServedWaveWords = 8;
-constexpr int kWaveExtraDoubles = 4 + kSlotCounters + kMatTableDoubles + kServedWaveWords;
+constexpr int kWaveExtraDoubles = 4 + 2 * kSlotCounters + kMatTableDoubles + kServedWaveWords;
 
 struct LaunchShape {
     int waves_per_block;
@@ -166,6 +177,7 @@ struct LaunchShape {
     int refill_min;
     int slots = 2;               // chosen by the launch sizing
     int slots_request = 0;       // the caller's choice (0: automatic, 1 or 2)
+    int chunk_batches = 0;       // 1: every chunk is its own error batch (no gathering)
 };
 
 // Kernel variants: geometry x estimator x source x precision x trace, and

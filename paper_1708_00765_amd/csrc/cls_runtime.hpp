@@ -85,8 +85,14 @@ using sched::batch_chunk_size;
 using sched::chunk_size;
 using sched::grouped_chunk_size;
 uint32_t unit_threshold(double q);
+// The device record of a run of p; every chunk is its own error batch
+// (batch_max = chunk) until the caller sets batch_max (batch_limit).
 void fill_dev_problem(const cls_problem *p, uint64_t histories, uint64_t seed, uint64_t chunk,
                       uint64_t trace_n, DevProblem *out);
+// Histories one error batch of a batch launch of shape s may gather
+// (DevProblem::batch_max): sched::batch_histories, or one chunk when
+// s.chunk_batches == 1.
+uint32_t batch_limit(uint64_t histories, uint64_t chunk, const LaunchShape &s);
 Variant variant_of(const cls_problem *p);
 bool same_variant(const Variant &a, const Variant &b);
 // Arguments of a launch over several problems: no NULL problem, one kernel

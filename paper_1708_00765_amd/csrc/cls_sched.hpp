@@ -1,7 +1,7 @@
 // Work-division rules of the CLS runtime: how a run is cut into chunks (work
-// items of consecutive histories; each chunk is also one batch of the
-// batch-means flux error) and how a server round shares its budget between
-// requests. Plain host C++ with no HIP dependency, so that the CPU tests can
+// items of consecutive histories), how many of a problem's histories one
+// batch of the batch-means flux error may gather, and how a server round
+// shares its budget between requests. Plain host C++ with no HIP dependency, so that the CPU tests can
 // compile and check it on its own.
 #pragma once
 
@@ -14,8 +14,8 @@
 namespace cls {
 namespace sched {
 
-// Chunks (batches of the flux error) a problem that runs with others keeps at
-// least, when its history count allows.
+// Batches of the flux error a problem keeps at least, when its history count
+// allows.
 constexpr uint64_t kMinErrorBatches = 256;
 
 // Flights after which a history is cut (and the run reports it), at most.
@@ -56,6 +56,17 @@ inline uint64_t grouped_chunk_size(uint64_t n, uint64_t waves_total, uint64_t ma
     // rounded down, so that n histories make at least kMinErrorBatches chunks
     const uint64_t c_err = std::max<uint64_t>(1, n / kMinErrorBatches);
     return std::max(c, std::min(std::min(cap, c_err), max_chunk));
+}
+
+// Histories of a problem of n histories, cut into chunks of `chunk`, that
+// one error batch may gather (a wave adds the chunks it takes of the problem
+// to its batch while they fit): n / kMinErrorBatches, so that the problem
+// keeps at least kMinErrorBatches batches, but never less than one chunk, and
+// below 2^31 (the kernel counts a batch's histories in 32 bits).
+inline uint64_t batch_histories(uint64_t n, uint64_t chunk)
+{
+    const uint64_t b = std::max<uint64_t>(chunk, n / kMinErrorBatches);
+    return std::min<uint64_t>(b, 1ull << 31);
 }
 
 // A batch whose problems hold `total` histories: chunks up to the size that

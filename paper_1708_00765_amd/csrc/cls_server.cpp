@@ -222,7 +222,7 @@ int served_bins(int nbins) { return std::min(CLS_MAX_BINS, std::max(kServedMinBi
 // A pool block: counters, sums, then (record_path 1) the device record.
 size_t record_offset(int nbins)
 {
-    return align256(C_COUNT * sizeof(uint64_t)) + align256((2 + 2 * (size_t)nbins) * sizeof(double));
+    return align256(C_COUNT * sizeof(uint64_t)) + align256(sums_words(nbins) * sizeof(double));
 }
 
 size_t block_bytes(const cls_server *s, int nbins)

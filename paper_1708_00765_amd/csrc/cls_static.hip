@@ -30,10 +30,10 @@ using namespace cls::rt;
 namespace {
 
 // Largest flux mesh of an allocation-free run, and the scratch size it needs:
-// the problem record, the queue words, C_COUNT counters and 2 + 2K sums, each
+// the problem record, the queue words, C_COUNT counters and 3 + 3K sums, each
 // section 256-byte aligned (40 KB for 2048 bins).
 constexpr int kStaticMaxBins = CLS_MAX_BINS;
-constexpr size_t kScratchBytes = 48 * 1024;
+constexpr size_t kScratchBytes = 64 * 1024;
 
 constexpr size_t kProbOff = 0;
 constexpr size_t kItemsOff = 512;                       // >= align256(sizeof(DevProblem))
@@ -41,7 +41,7 @@ constexpr size_t kCountersOff = kItemsOff + 256;        // [0] = 0, [1] = items,
 constexpr size_t kSumsOff = kCountersOff + 256;         // C_COUNT u64 counters
 static_assert(sizeof(DevProblem) <= kItemsOff - kProbOff, "problem record exceeds its scratch section");
 static_assert(C_COUNT * sizeof(uint64_t) <= 256, "counters exceed their scratch section");
-static_assert(kSumsOff + (2 + 2 * (size_t)kStaticMaxBins) * sizeof(double) <= kScratchBytes,
+static_assert(kSumsOff + sums_words(kStaticMaxBins) * sizeof(double) <= kScratchBytes,
               "flux sums of the largest mesh exceed the scratch array");
 
 }  // namespace
@@ -66,7 +66,7 @@ __global__ void static_setup_kernel(DevProblem prob, DevProblem *dst, uint64_t *
         items[3] = 0;
     }
     for (int i = t; i < C_COUNT; i += (int)blockDim.x) prob.counters[i] = 0ull;
-    for (int i = t; i < 2 + 2 * prob.nbins; i += (int)blockDim.x) prob.sums[i] = 0.0;
+    for (int i = t; i < (int)sums_words(prob.nbins); i += (int)blockDim.x) prob.sums[i] = 0.0;
 }
 
 // Device address of `scratch` per device, taken once per device with that
@@ -126,6 +126,7 @@ extern "C" cls_status cls_run_static(const cls_problem *p, uint64_t histories, u
     const uint64_t n_items = (histories + chunk - 1) / chunk;
     DevProblem prob;
     fill_dev_problem(p, histories, seed, chunk, 0, &prob);
+    prob.batch_max = batch_limit(histories, chunk, used);
     prob.counters = (uint64_t *)(base + kCountersOff);
     prob.sums = (double *)(base + kSumsOff);
     prob.record = (uint64_t *)d_record;

@@ -17,20 +17,24 @@
 //  * every step consumes exactly one Philox block per lane (source step or
 //    flight), so the random-number work never diverges;
 //  * the source and the scattering direction share one direction sampler;
-//  * each wave owns two LDS tally buffers ("slots"), one per work chunk in
-//    flight: histories of the chunk being started go to one, stragglers of the
-//    previous chunk finish in the other, and a chunk's buffer is flushed to
-//    HBM with FP64 atomics once its last history ends, so a chunk is exactly
-//    one batch of the batch-means flux error with no tail stall (with fine
-//    meshes a launch may give each wave one buffer, which then waits for its
-//    chunk's last history before it claims the next);
+//  * each wave owns two LDS tally buffers ("slots"), one per batch of the
+//    batch-means flux error in flight: histories of the batch being filled go
+//    to one, stragglers of the previous batch finish in the other, and a
+//    batch's buffer is flushed to HBM with FP64 atomics once its last history
+//    ends (with fine meshes a launch may give each wave one buffer, which
+//    then waits for its batch's last history before it starts the next);
+//  * work comes in chunks of consecutive histories from one queue per
+//    problem, and a wave keeps taking chunks of its problem: in a batch launch
+//    the chunks a wave takes of one problem join the batch it is filling up
+//    to the problem's batch size, so a launch flushes about one batch per wave
+//    and problem instead of one per chunk (served rounds flush every chunk);
 //  * track-length flux goes to the LDS buffer in difference form (four LDS
 //    FP64 atomics per flight whatever the number of bins crossed); the flush
 //    prefix-scans it across the wave;
 //  * per-history scores and event counts are summed in each lane's registers
-//    over its histories in a slot and reach the slot's LDS counters only when
-//    the lane changes slot or the slot is flushed; flights and collisions are
-//    derived at the flush.
+//    over its histories of one chunk and reach the slot's LDS counters when
+//    the lane takes a history of another chunk or the slot is flushed;
+//    collisions and lateral reflections are derived when the record is made.
 #include <type_traits>
 
 #include "cls_internal.hpp"
@@ -130,12 +134,21 @@ __device__ __forceinline__ uint64_t fnv_event(uint64_t h, int ev, int m, int bin
 // ---------------------------------------------------------------------------
 // per-slot bookkeeping (wave-uniform values)
 // ---------------------------------------------------------------------------
-// Counters of a chunk slot: the first S_STORED are 64-bit LDS counters that the
-// lanes add their sums to; collisions and lateral reflections are derived at the
-// flush (a collision is a scatter or an absorption; a flight ends in a leak, an
-// absorption, a scatter, an interface crossing or a lateral mirror).
-enum SlotCtr : int { S_T = 0, S_R, S_A, S_CAP, S_FLIGHTS, S_SCAT, S_INT, S_STORED, S_COLL = S_STORED, S_LAT, S_NCTR };
-static_assert(S_STORED <= kSlotCounters, "slot counters do not fit their LDS area");
+// Event counters of a slot, in the order of the global counters they are
+// added to (slot_ctr_to_global); collisions and lateral reflections are
+// derived in the record (record_into).
+enum SlotCtr : int { S_T = 0, S_R, S_A, S_CAP, S_FLIGHTS, S_SCAT, S_INT, S_NCTR };
+// Their 64-bit LDS words: transmitted and reflected share one (low and high
+// half), absorbed and capped another (each half counts histories of the
+// batch, below 2^31, so the halves never carry into each other); flights,
+// scatters and interface crossings have one each, and the last word of the
+// slot's area holds the histories of its batch.
+enum SlotWord : int { W_TR = 0, W_AC, W_FLIGHTS, W_SCAT, W_INT, W_STORED };
+constexpr int W_TOTAL = kSlotCounters - 1;
+// Two words of slot 0's area that no counter uses hold, in a batch launch, the
+// wave's problem and its pending chunk (see the kernel).
+constexpr int W_HOME = W_STORED, W_PEND = W_STORED + 1;
+static_assert(W_PEND < W_TOTAL, "slot counters do not fit their LDS area");
 static_assert(EV_LEAK_XHI - EV_LEAK_XHI == S_T && EV_LEAK_XHI - EV_LEAK_XLO == S_R &&
                   EV_LEAK_XHI - EV_ABSORB == S_A,
               "outcome counters follow the leak and absorption event codes");
@@ -512,6 +525,8 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
 // wave's vector memory operations, stores and atomics included, are complete.
 constexpr int kWaitVmcnt0 = 0x0F70;
 
+// (h0, cnt, next: the chunk being handed out; live: the slot's histories in
+// flight; the histories of the slot's batch so far are an LDS word, W_TOTAL)
 struct SlotState {
     uint64_t h0;
     uint32_t cnt, next, live;
@@ -557,8 +572,16 @@ __device__ __forceinline__ void record_into(PR &P, uint64_t *rec, int t, int nt)
     const double n = (double)tally_u<L2>(C + C_HISTORIES);
     const double B = (double)tally_u<L2>(C + C_BATCHES);
     double *out = (double *)(rec + C_COUNT);
-    for (int i = t; i < C_COUNT; i += nt) rec[i] = tally_u<L2>(C + i);
+    for (int i = t; i < C_COUNT; i += nt)
+        if (i != C_COLLISIONS && i != C_LATERAL) rec[i] = tally_u<L2>(C + i);
     if (t == 0) {
+        // derived counts: a collision is a scatter or an absorption; a flight
+        // ends in a leak, an absorption, a scatter, an interface crossing or a
+        // lateral mirror (a capped history's refused step is no flight)
+        const uint64_t sc = tally_u<L2>(C + C_SCATTERS), ab = tally_u<L2>(C + C_ABSORBED);
+        rec[C_COLLISIONS] = sc + ab;
+        rec[C_LATERAL] = tally_u<L2>(C + C_FLIGHTS) - (tally_u<L2>(C + C_TRANSMITTED) + tally_u<L2>(C + C_REFLECTED) +
+                                                       ab + sc + tally_u<L2>(C + C_INTERFACES));
         double mu, sg;
         const double nt_ = (double)tally_u<L2>(C + C_TRANSMITTED);
         const double nr_ = (double)tally_u<L2>(C + C_REFLECTED);
@@ -572,14 +595,21 @@ __device__ __forceinline__ void record_into(PR &P, uint64_t *rec, int t, int nt)
         mean_sigma(tally_d<L2>(P.sums), tally_d<L2>(P.sums + 1), n, &mu, &sg);
         out[R_TOTAL] = mu; out[R_SIGMA_TOTAL] = sg;
     }
-    // batch means: chunk b holds n_b histories with bin score s_b; with
-    // S = sum s_b and Q = sum s_b^2 / n_b the per-history variance is
-    // (Q - S^2/N) / (B - 1) and the error of the mean its square root over N.
+    // batch means: batch b holds n_b histories with bin score s_b, and m is
+    // the mean per history. sum (s_b - n_b m)^2 = P - 2 m R + m^2 M has the
+    // expectation sigma^2 (N - M / N) (sigma^2 the per-history variance)
+    // whatever the batch sizes; every history's squared score enters it with
+    // weight one, and a batch mean that drifts with the batch size enters it
+    // only squared (with equal batches it is the usual (B - 1) n times the
+    // variance of the batch means). The error of the mean is sqrt(sigma^2 / N).
+    const double M = tally_d<L2>(P.sums + 2 + 3 * K);
+    const double den = n > 0.0 ? n - M / n : 0.0;
     for (int k = t; k < K; k += nt) {
         const double S = tally_d<L2>(P.sums + 2 + k);
-        const double Q = tally_d<L2>(P.sums + 2 + K + k);
+        const double Pk = tally_d<L2>(P.sums + 2 + K + k);
+        const double Rk = tally_d<L2>(P.sums + 2 + 2 * K + k);
         const double mu = n > 0.0 ? S / n : 0.0;
-        double var = B > 1.0 ? (Q - S * mu) / (B - 1.0) : 0.0;
+        double var = (B > 1.0 && den > 0.0) ? (Pk - mu * (2.0 * Rk - mu * M)) / den : 0.0;
         var = var > 0.0 ? var : 0.0;
         out[R_HEADER + k] = mu / P.dx;
         out[R_HEADER + K + k] = (n > 0.0 && B > 1.0) ? sqrt(var / n) / P.dx : 0.0;
@@ -588,23 +618,22 @@ __device__ __forceinline__ void record_into(PR &P, uint64_t *rec, int t, int nt)
 
 // Move a lane's sums to the LDS counters of its slot (a lane that finished no
 // history there holds none) and clear them.
-// The counters are 32-bit: the host caps a history's flights at
-// (2^32 - 1) / (histories per chunk), so no sum over a chunk can wrap.
+// A lane's sums are 32-bit and cover its histories of one chunk: the host caps
+// a history's flights at (2^32 - 1) / (histories per chunk), so they cannot
+// wrap; the slot's counters, over a whole batch, are 64-bit.
 template <typename R>
-__device__ __forceinline__ void lane_to_slot(Lane<R> &L, double *wsum, uint32_t *wctr)
+__device__ __forceinline__ void lane_to_slot(Lane<R> &L, double *wsum, uint64_t *wctr)
 {
     if ((L.n_t | L.n_r | L.n_a | L.n_cap) != 0u) {
         double *ss = wsum + 2 * L.slot;
         lds_add(ss, L.ssum);
         lds_add(ss + 1, L.ssq);
-        uint32_t *c = wctr + L.slot * kSlotCounters;
-        atomicAdd(c + S_T, L.n_t);
-        atomicAdd(c + S_R, L.n_r);
-        atomicAdd(c + S_A, L.n_a);
-        atomicAdd(c + S_CAP, L.n_cap);
-        atomicAdd(c + S_FLIGHTS, L.n_fl);
-        atomicAdd(c + S_SCAT, L.n_scat);
-        atomicAdd(c + S_INT, L.n_int);
+        unsigned long long *c = (unsigned long long *)(wctr + L.slot * kSlotCounters);
+        atomicAdd(c + W_TR, (unsigned long long)L.n_t | ((unsigned long long)L.n_r << 32));
+        atomicAdd(c + W_AC, (unsigned long long)L.n_a | ((unsigned long long)L.n_cap << 32));
+        atomicAdd(c + W_FLIGHTS, (unsigned long long)L.n_fl);
+        atomicAdd(c + W_SCAT, (unsigned long long)L.n_scat);
+        atomicAdd(c + W_INT, (unsigned long long)L.n_int);
     }
     L.ssum = 0.0;
     L.ssq = 0.0;
@@ -612,19 +641,22 @@ __device__ __forceinline__ void lane_to_slot(Lane<R> &L, double *wsum, uint32_t 
     L.n_int = L.n_scat = L.n_fl = 0u;
 }
 
-// Move a finished chunk's tallies from its LDS slot to HBM: the flux bins
+// Move a finished batch's tallies from its LDS slot to HBM: the flux bins
 // (prefix-scanned first for the difference-form track-length tally) as the
-// chunk's batch sum S and its square over the chunk size Q, the history score
-// sums and the event counters. Leaves the LDS slot zeroed and the slot closed.
+// batch sum s_b into S, s_b^2 into P and n_b s_b into R, n_b^2 into M (the
+// batch of n_b histories), the history score sums and the event counters.
+// Leaves the LDS slot zeroed and the slot closed.
 template <int EST, bool SERVED>
-__device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, double *b, double *ssum, uint32_t *c,
+__device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, double *b, double *ssum, uint64_t *c,
                                            int lane)
 {
     ConstProblem &P = ((ConstProblem *)A.probs)[S.pid];
     const int KK = P.nbins;
     double *Sk = P.sums + 2;
-    double *Qk = P.sums + 2 + KK;
-    const double inv_n = 1.0 / (double)S.cnt;
+    double *Pk = P.sums + 2 + KK;
+    double *Rk = P.sums + 2 + 2 * KK;
+    const uint64_t total = readlane64(c[W_TOTAL], 0);
+    const double nb = (double)total;
     // Track length: the four entries of each flight sum to zero, so from the
     // last nonzero entry of the difference buffer on the exact running sum is
     // zero (no track reached those bins); the accumulated entries would leave
@@ -649,35 +681,41 @@ __device__ __forceinline__ void flush_slot(SlotState &S, const TrackArgs &A, dou
             v = wave_inclusive_scan(v, lane) + carry;
             carry = __shfl(v, 63, 64);
         }
-        if (k < kend && v != 0.0) {
-            atomicAdd(Sk + k, v);
-            atomicAdd(Qk + k, v * v * inv_n);
-        }
-        if (k <= KK) b[k] = 0.0;
+        if (k < kend && v != 0.0) atomicAdd(Sk + k, v);
+        if (k <= KK) b[k] = (k < kend) ? v : 0.0;
+    }
+    for (int k = lane; k < kend; k += 64) {
+        const double v = b[k];
+        if (v != 0.0) atomicAdd(Pk + k, v * v);
+    }
+    for (int k = lane; k < kend; k += 64) {
+        const double v = b[k];
+        if (v != 0.0) atomicAdd(Rk + k, v * nb);
+        b[k] = 0.0;
     }
     const double st = ssum[0];
     const double st2 = ssum[1];
-    // one counter per lane: lanes 0..S_NCTR-1 move them to HBM. Collisions and
-    // lateral mirror reflections are derived: a collision is a scatter or an
-    // absorption; a flight ends in a leak (T, R), an absorption, a scatter, an
-    // interface crossing or a lateral mirror (a capped history's refused step
-    // is no flight).
-    uint64_t cv = lane < S_STORED ? c[lane] : 0u;
-    const uint64_t n_t = c[S_T], n_r = c[S_R], n_a = c[S_A], n_sc = c[S_SCAT], n_in = c[S_INT], n_fl = c[S_FLIGHTS];
-    if (lane == S_COLL) cv = n_sc + n_a;
-    if (lane == S_LAT) cv = n_fl - (n_t + n_r + n_a + n_sc + n_in);
-    if (lane < S_STORED) c[lane] = 0u;
+    // one counter per lane: lanes 0..S_NCTR-1 move them to HBM (the first four
+    // are the halves of two words)
+    static_assert(S_T == 0 && S_R == 1 && S_A == 2 && S_CAP == 3 && S_FLIGHTS == W_FLIGHTS + 2 &&
+                      S_SCAT == W_SCAT + 2 && S_INT == W_INT + 2 && W_TR == 0 && W_AC == 1,
+                  "slot counters map onto their LDS words");
+    const int w = lane < 4 ? (lane >> 1) : lane - 2;
+    const uint64_t v = lane < S_NCTR ? c[w] : 0u;
+    const uint64_t cv = lane < 4 ? ((lane & 1) ? (v >> 32) : (v & 0xFFFFFFFFull)) : v;
+    if (lane < W_STORED) c[lane] = 0u;
     const int slot_ctr_to_global[S_NCTR] = {C_TRANSMITTED, C_REFLECTED, C_ABSORBED, C_CAPPED, C_FLIGHTS,
-                                            C_SCATTERS, C_INTERFACES, C_COLLISIONS, C_LATERAL};
+                                            C_SCATTERS, C_INTERFACES};
     unsigned long long *Cg = (unsigned long long *)P.counters;
     if (lane < S_NCTR && cv != 0u) atomicAdd(Cg + slot_ctr_to_global[lane], (unsigned long long)cv);
     if (lane == 0) {
         ssum[0] = 0.0;
         ssum[1] = 0.0;
-        atomicAdd(Cg + C_HISTORIES, (unsigned long long)S.cnt);
+        atomicAdd(Cg + C_HISTORIES, (unsigned long long)total);
         atomicAdd(Cg + C_BATCHES, 1ull);
         atomicAdd(P.sums + 0, st);
         atomicAdd(P.sums + 1, st2);
+        atomicAdd(P.sums + 2 + 3 * KK, nb * nb);
     }
     S.open = 0;
     if (SERVED) {
@@ -806,10 +844,65 @@ __device__ __forceinline__ int event_step_kind(int kind, Lane<R> &L, const Prm<R
 #undef CLS_KIND_CASE
 }
 
+// ---------------------------------------------------------------------------
+// batch launches: one work queue per problem
+// ---------------------------------------------------------------------------
+// A problem's chunks are handed out by a counter of its own (C_QUEUE_HEAD), and
+// a wave takes chunks of one problem for as long as that problem has any, so
+// that the chunks it takes can join one error batch. A wave starts on the
+// problem that holds its share of the launch (wave w of W: chunk w * total / W
+// in the problems' order). Once its problem has none left it goes through the
+// other problems in order, once: a problem whose counter was read at or beyond
+// its chunk count (counters only grow), or whose fetch-add returned such a
+// value, has none left, so every wave leaves after at most one pass.
+constexpr uint64_t kNoChunk = ~0ull;
+
+__device__ __forceinline__ uint64_t queue_fetch(const TrackArgs &A, int q, int lane)
+{
+    uint64_t got = 0;
+    if (lane == 0) got = atomicAdd((unsigned long long *)(A.probs[q].counters + C_QUEUE_HEAD), 1ull);
+    return readlane64(got, 0);
+}
+
+// The next chunk for a wave whose problem is *hp: its index among the chunks
+// of problem *hp (updated), or kNoChunk when no problem has any left.
+__device__ __forceinline__ uint64_t batch_claim(const TrackArgs &A, int lane, int *hp)
+{
+    const uint64_t *starts = A.item_start;
+    const int n = A.nprobs;
+    const int p = *hp;
+    uint64_t got = queue_fetch(A, p, lane);
+    if (got < starts[p + 1] - starts[p]) return ((ConstProblem *)A.probs)[p].chunk_base + got;
+    // the others, 64 at a time: each lane reads one counter
+    for (int base = 1; base < n; base += 64) {
+        const int off = base + lane;
+        int q = p + off;
+        if (q >= n) q -= n;
+        bool left = false;
+        if (off < n) {
+            const uint64_t head =
+                __hip_atomic_load(A.probs[q].counters + C_QUEUE_HEAD, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            left = head < starts[q + 1] - starts[q];
+        }
+        uint64_t m = ballot(left);
+        while (m != 0) {
+            int r = p + base + __builtin_ctzll(m);
+            if (r >= n) r -= n;
+            m &= m - 1;
+            got = queue_fetch(A, r, lane);
+            if (got < starts[r + 1] - starts[r]) {
+                *hp = r;
+                return ((ConstProblem *)A.probs)[r].chunk_base + got;
+            }
+        }
+    }
+    return kNoChunk;
+}
+
 // The flush of a slot: with the estimator of the kernel, or (served rounds)
 // of the slot's problem.
 template <int EST, bool SERVED>
-__device__ __forceinline__ void flush_any(SlotState &S, const TrackArgs &A, double *b, double *ssum, uint32_t *c,
+__device__ __forceinline__ void flush_any(SlotState &S, const TrackArgs &A, double *b, double *ssum, uint64_t *c,
                                           int lane)
 {
     if constexpr (EST >= 0) {
@@ -840,21 +933,39 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
     // wave's claim state
     double *const wbuf = lds + (size_t)wid * ((size_t)nslots * (size_t)KP + kWaveExtraDoubles);
     double *const wsum = wbuf + nslots * KP;
-    uint32_t *const wctr = (uint32_t *)(wsum + 4);    // [slot][kSlotCounters]
-    MatRow<R> *const wmat = (MatRow<R> *)(wsum + 4 + kSlotCounters);   // [slot][material]
-    uint64_t *const wsrv = (uint64_t *)(wsum + 4 + kSlotCounters + kMatTableDoubles);
+    uint64_t *const wctr = (uint64_t *)(wsum + 4);    // [slot][kSlotCounters]
+    MatRow<R> *const wmat = (MatRow<R> *)(wsum + 4 + 2 * kSlotCounters);   // [slot][material]
+    uint64_t *const wsrv = (uint64_t *)(wsum + 4 + 2 * kSlotCounters + kMatTableDoubles);
     for (int i = lane; i < nslots * KP + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
 
-    // Wave-uniform state of the two chunk slots, kept as two named records
-    // (never indexed by a run-time value, so that they stay in scalar
-    // registers): C receives new histories and owns tally buffer cp, O is the
-    // other one (buffer cp ^ 1) whose stragglers may still be in flight. With
-    // a single buffer (large meshes) O stays closed and a new chunk is taken
-    // only once C has been flushed.
+    // Wave-uniform state of the two slots, kept as two named records (never
+    // indexed by a run-time value, so that they stay in scalar registers): C
+    // receives new histories and owns tally buffer cp, O is the other one
+    // (buffer cp ^ 1) whose stragglers may still be in flight. With a single
+    // buffer (large meshes) O stays closed and a new batch starts only once C
+    // has been flushed.
     SlotState C = {0, 0, 0, 0, 0, 0}, O = {0, 0, 0, 0, 0, 0};
     int cp = 0;
     bool queue_empty = false;
-    const uint64_t total_items = SERVED ? 0 : A.item_start[A.nprobs];
+    // batch launches: the wave's problem and a chunk of it taken but not yet
+    // placed (kNoChunk: none, else it waits for a free slot), kept in the
+    // wave's LDS words (touched only where chunks are taken)
+    if (!SERVED) {
+        const __attribute__((address_space(4))) uint64_t *starts =
+            (const __attribute__((address_space(4))) uint64_t *)A.item_start;
+        const uint64_t wpb = blockDim.x >> 6;
+        const uint64_t w = (uint64_t)blockIdx.x * wpb + (uint64_t)__builtin_amdgcn_readfirstlane(wid);
+        const uint64_t t = w * starts[A.nprobs] / ((uint64_t)gridDim.x * wpb);
+        int l = 0, hi = A.nprobs;
+        while (hi - l > 1) {
+            const int mid = (l + hi) >> 1;
+            if (starts[mid] <= t) l = mid; else hi = mid;
+        }
+        if (lane == 0) {
+            wctr[W_HOME] = (uint64_t)l;
+            wctr[W_PEND] = kNoChunk;
+        }
+    }
     // served rounds: the wave's claim state lives in its LDS words (wsrv,
     // ServedWave): it is touched only when the wave claims or has nothing to
     // run, and kept out of the scalar registers the tracking loop needs. While
@@ -887,13 +998,12 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
         // chunk cannot serve wait for the next step.
         uint64_t dead = ballot(!L.alive);
         if (dead != 0 && (dead == ~0ull || popc(dead) >= (uint32_t)A.refill_min)) {
-            const bool slot_free = nslots == 2 ? ((!C.open || C.next == C.cnt) && !O.open) : !C.open;
-            if (slot_free && !queue_empty) {
-                // the next chunk: its problem and its index among the problem's chunks
-                int lo = -1;
-                uint64_t chunk_index = 0;
-                if (SERVED) {
-                    lo = kClaimWait;
+            if constexpr (SERVED) {
+                // a served round: every chunk is a batch of its own
+                const bool slot_free = nslots == 2 ? ((!C.open || C.next == C.cnt) && !O.open) : !C.open;
+                if (slot_free && !queue_empty) {
+                    uint64_t chunk_index = 0;
+                    int lo = kClaimWait;
                     const uint64_t poll_wait = lds_uniform(wsrv + SV_POLL_WAIT);
                     if (poll_wait == 0) {
                         lo = served_claim(A, lane, wsrv, &chunk_index);
@@ -911,45 +1021,71 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
                     } else if (lane == 0) {
                         wsrv[SV_POLL_WAIT] = poll_wait - 1;
                     }
-                } else {
-                    uint64_t got = 0;
-                    if (lane == 0) got = atomicAdd((unsigned long long *)A.queue_head, 1ull);
-                    // lane 0's value, made wave-uniform so that the slot state
-                    // derived from it stays in scalar registers
-                    const uint64_t item = readlane64(got, 0);
-                    if (item < total_items) {
-                        const __attribute__((address_space(4))) uint64_t *starts =
-                            (const __attribute__((address_space(4))) uint64_t *)A.item_start;
-                        int l = 0, hi = A.nprobs;
-                        while (hi - l > 1) {
-                            const int mid = (l + hi) >> 1;
-                            if (starts[mid] <= item) l = mid; else hi = mid;
+                    if (lo >= 0) {
+                        ConstProblem &P = ((ConstProblem *)A.probs)[lo];
+                        const uint64_t first = chunk_index * P.chunk;
+                        const uint64_t rest = P.histories - first;
+                        // the new chunk goes to the free slot, which becomes current
+                        if (nslots == 2) {
+                            O = C;
+                            cp ^= 1;
                         }
-                        lo = l;
-                        chunk_index = ((ConstProblem *)A.probs)[lo].chunk_base + item - starts[lo];
+                        C.h0 = first;
+                        C.cnt = (uint32_t)(rest < P.chunk ? rest : P.chunk);
+                        C.next = 0;
+                        C.live = 0;
+                        C.pid = lo;
+                        C.open = 1;
+                        if (lane == 0) wctr[cp * kSlotCounters + W_TOTAL] = C.cnt;
+                        // the new slot's material rows; no lane of this wave reads
+                        // them before its next event step, and a wave's LDS
+                        // operations complete in order
+                        if (lane < 2) wmat[2 * cp + lane] = mat_row<R>(P, lane);
                     }
                 }
-                if (lo < 0) {
-                    if (!SERVED) queue_empty = true;
-                } else {
-                    ConstProblem &P = ((ConstProblem *)A.probs)[lo];
-                    const uint64_t first = chunk_index * P.chunk;
-                    const uint64_t rest = P.histories - first;
-                    // the new chunk goes to the free slot, which becomes current
-                    if (nslots == 2) {
-                        O = C;
-                        cp ^= 1;
+            } else {
+                // a batch launch: the next chunk is taken once the current one
+                // is handed out; it joins the batch of slot C when it is of the
+                // same problem and fits, else it opens a batch in a free slot
+                // (and waits while there is none)
+                if (!C.open || C.next == C.cnt) {
+                    uint64_t pend = lds_uniform(wctr + W_PEND);
+                    int hp = (int)lds_uniform(wctr + W_HOME);
+                    if (pend == kNoChunk && !queue_empty) {
+                        pend = batch_claim(A, lane, &hp);
+                        if (pend == kNoChunk) queue_empty = true;
+                        if (lane == 0) wctr[W_HOME] = (uint64_t)hp;
                     }
-                    C.h0 = first;
-                    C.cnt = (uint32_t)(rest < P.chunk ? rest : P.chunk);
-                    C.next = 0;
-                    C.live = 0;
-                    C.pid = lo;
-                    C.open = 1;
-                    // the new slot's material rows; no lane of this wave reads
-                    // them before its next event step, and a wave's LDS
-                    // operations complete in order
-                    if (lane < 2) wmat[2 * cp + lane] = mat_row<R>(P, lane);
+                    if (pend != kNoChunk) {
+                        ConstProblem &P = ((ConstProblem *)A.probs)[hp];
+                        const uint64_t first = pend * P.chunk;
+                        const uint64_t rest = P.histories - first;
+                        const uint32_t cnt = (uint32_t)(rest < P.chunk ? rest : P.chunk);
+                        uint64_t *const ctot = wctr + cp * kSlotCounters + W_TOTAL;
+                        const uint64_t total = C.open ? lds_uniform(ctot) : 0;
+                        if (C.open && C.pid == hp && total + cnt <= (uint64_t)P.batch_max) {
+                            C.h0 = first;
+                            C.cnt = cnt;
+                            C.next = 0;
+                            if (lane == 0) *ctot = total + cnt;
+                            pend = kNoChunk;
+                        } else if (!C.open || (nslots == 2 && !O.open)) {
+                            if (C.open) {
+                                O = C;
+                                cp ^= 1;
+                            }
+                            C.h0 = first;
+                            C.cnt = cnt;
+                            C.next = 0;
+                            C.live = 0;
+                            C.pid = hp;
+                            C.open = 1;
+                            if (lane == 0) wctr[cp * kSlotCounters + W_TOTAL] = cnt;
+                            if (lane < 2) wmat[2 * cp + lane] = mat_row<R>(P, lane);
+                            pend = kNoChunk;
+                        }
+                    }
+                    if (lane == 0) wctr[W_PEND] = pend;
                 }
             }
             if (C.open && C.next < C.cnt) {
@@ -962,8 +1098,9 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
                 // lanes' registers, where selects would first copy them)
                 const bool nw = !L.alive && r < take;
                 if (nw) {
-                    // sums of the lane's histories in the other slot go there first
-                    if (L.slot != cp) lane_to_slot(L, wsum, wctr);
+                    // sums of the lane's histories in the other slot, or of an
+                    // earlier chunk of this slot's batch, go to the slot first
+                    if (L.slot != cp || L.h - C.h0 >= (uint64_t)C.cnt) lane_to_slot(L, wsum, wctr);
                     L.slot = cp;
                     L.h = C.h0 + C.next + r;
                     L.step = 0u;
@@ -1053,8 +1190,8 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
                 L.alive = false;
             }
 
-            // ------------- flush chunks whose last history ended -------------
-            // (every lane that ran histories of the chunk is idle now and holds
+            // ------------- flush batches whose last history ended ------------
+            // (every lane that ran histories of the batch is idle now and holds
             // their sums; they join the slot's counters first)
             if (C.open && C.next == C.cnt && C.live == 0) {
                 if (L.slot == cp) lane_to_slot(L, wsum, wctr);
@@ -1096,7 +1233,7 @@ __global__ void __launch_bounds__(512) served_kernel(TrackArgs A)
 __global__ void reset_kernel(const DevProblem *probs, uint64_t *queue_head)
 {
     const DevProblem &P = probs[blockIdx.x];
-    const int n = 2 + 2 * P.nbins;
+    const int n = (int)sums_words(P.nbins);
     for (int i = threadIdx.x; i < n; i += blockDim.x) P.sums[i] = 0.0;
     for (int i = threadIdx.x; i < C_COUNT; i += blockDim.x) P.counters[i] = 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) *queue_head = 0ull;
@@ -1125,7 +1262,7 @@ __global__ void __launch_bounds__(64) finalize_clear_kernel(const DevProblem *pr
     const DevProblem &P = probs[blockIdx.x];
     record_into<true>(P, P.record, (int)threadIdx.x, (int)blockDim.x);
     __syncthreads();
-    for (int i = threadIdx.x; i < 2 + 2 * P.nbins; i += blockDim.x)
+    for (int i = threadIdx.x; i < (int)sums_words(P.nbins); i += blockDim.x)
         __hip_atomic_store(P.sums + i, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int i = threadIdx.x; i < C_COUNT; i += blockDim.x)
         __hip_atomic_store(P.counters + i, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

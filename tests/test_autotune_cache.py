@@ -33,7 +33,8 @@ def _tuned(cls, monkeypatch, path, lines, **problem):
 def test_cached_configuration_is_used(cls, monkeypatch, tmp_path):
     lines = ["gfx950/g3/e1/s0/fp32/k128 4 0 16384 8 2"]
     cfg, rate = _tuned(cls, monkeypatch, tmp_path / "c.txt", lines, d=3, nbins=100, flags=cls.CLS_F_FP32)
-    assert cfg == {"waves_per_block": 4, "blocks_per_cu": 0, "max_chunk": 16384, "refill_min": 8, "slots": 2}
+    assert cfg == {"waves_per_block": 4, "blocks_per_cu": 0, "max_chunk": 16384, "refill_min": 8, "slots": 2,
+                   "chunk_batches": 0}
     assert rate == 0.0
     assert cls.cls_get_launch_config() == cfg      # the process-wide configuration now
     cls.cls_set_launch_config(0, 0, 0, 0)
@@ -75,7 +76,8 @@ def test_last_line_wins_and_old_lines_read(cls, monkeypatch, tmp_path):
              "gfx950/g3/e1/s0/fp32/k128 8 0 65536 16",      # four fields: automatic buffer count
              "gfx950/g2/e1/s0/fp32/k128 1 0 4096 4 2"]
     cfg, _ = _tuned(cls, monkeypatch, tmp_path / "c.txt", lines, d=3, nbins=100, flags=cls.CLS_F_FP32)
-    assert cfg == {"waves_per_block": 8, "blocks_per_cu": 0, "max_chunk": 65536, "refill_min": 16, "slots": 0}
+    assert cfg == {"waves_per_block": 8, "blocks_per_cu": 0, "max_chunk": 65536, "refill_min": 16, "slots": 0,
+                   "chunk_batches": 0}
     cls.cls_set_launch_config(0, 0, 0, 0)
 
 

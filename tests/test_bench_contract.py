@@ -51,7 +51,7 @@ def test_bench_line_on_a_small_run():
     assert j["fp64_plain"]["value"] > 0
     lc = j["launch_config"]            # the autotuned configuration, the default one timed beside it
     assert lc["default_config_value"] > 0 and set(lc["autotuned_config"]) == {
-        "waves_per_block", "blocks_per_cu", "max_chunk", "refill_min", "slots"}
+        "waves_per_block", "blocks_per_cu", "max_chunk", "refill_min", "slots", "chunk_batches"}
     acc = j["fp32_vs_fp64_same_streams"]
     assert acc["bins_compared"] == 32 * 1000 and set(acc["violations"]) == {"scalars", "profiles", "bins"}
     orc = j["fp32_vs_oracle"]

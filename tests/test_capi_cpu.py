@@ -98,9 +98,11 @@ def test_launch_config_validation(cls):
         cls.cls_set_launch_config(refill_min=65)
     with pytest.raises(cls.ClsError):
         cls.cls_set_launch_config(slots=3)
-    cls.cls_set_launch_config(2, 4, 1024, 8, 1)
+    with pytest.raises(cls.ClsError):
+        cls.cls_set_launch_config(chunk_batches=2)
+    cls.cls_set_launch_config(2, 4, 1024, 8, 1, 1)
     assert cls.cls_get_launch_config() == {"waves_per_block": 2, "blocks_per_cu": 4, "max_chunk": 1024,
-                                           "refill_min": 8, "slots": 1}
+                                           "refill_min": 8, "slots": 1, "chunk_batches": 1}
     cls.cls_set_launch_config(0, 0, 0, 0)
     assert cls.cls_get_launch_config() == old
 

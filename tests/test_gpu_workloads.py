@@ -211,9 +211,8 @@ def test_results_do_not_depend_on_launch_shape_and_autotune(cls, fp32):
 
 
 def test_batch_chunks_keep_error_batches(cls):
-    """In a batch a problem's chunks only grow (never more chunks than alone),
-    and it keeps at least min(256, n / 64) of them, the batches of its per-bin
-    flux error; counts stay those of the lone run."""
+    """A problem keeps at least min(256, n / 64) batches of its per-bin flux
+    error, in a batch of problems as alone; counts stay those of the lone run."""
     specs = workload("ext2d_batched", histories=None)[:24]
     alone = [run_gpu(s, fp32=True)[0] for s in specs]
     probs = [gpu_problem(s, fp32=True) for s in specs]
@@ -223,8 +222,7 @@ def test_batch_chunks_keep_error_batches(cls):
             t, _, fsig = cls.cls_read_tallies(p, s.nbins)
             g2 = tallies_dict(t)
             _print(s.name, "histories", s.histories, "chunks alone", g1["batches"], "in the batch", g2["batches"])
-            assert g2["batches"] <= g1["batches"], s.name
-            assert g2["batches"] >= min(256, s.histories // 64), s.name
+            assert min(g1["batches"], g2["batches"]) >= min(256, s.histories // 64), s.name
             for k in COUNTS:
                 assert g1[k] == g2[k], (s.name, k)
             assert np.all(np.isfinite(fsig))
@@ -304,19 +302,68 @@ def test_served_small_requests_overtake_big_ones_and_keep_results(cls):
             cls.cls_destroy_problem(p)
 
 
+def test_gathered_error_batches(cls):
+    """A wave gathers the chunks it takes of one problem into one error batch
+    (default) instead of flushing every chunk (chunk_batches = 1): on the cube
+    workload (8 sets, 2e6 histories each) the counts are equal, the flux agrees
+    to summation order, every set keeps at least 256 batches and no more than
+    chunks, the sets together have at most half as many batches as chunks, and
+    the per-bin batch-means errors of the two batchings agree within their
+    statistical spread."""
+    specs = workload("cube3d_track", histories=2_000_000)
+    probs = [gpu_problem(s, fp32=True) for s in specs]
+    out = {}
+    try:
+        for cb in (1, 0):
+            cls.cls_set_launch_config(chunk_batches=cb)
+            cls.cls_run_batch(probs, [s.histories for s in specs], [s.seed for s in specs])
+            out[cb] = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(probs, specs)]
+    finally:
+        cls.cls_set_launch_config(0, 0, 0, 0)
+        for p in probs:
+            cls.cls_destroy_problem(p)
+    for s, (t1, f1, e1), (t0, f0, e0) in zip(specs, out[1], out[0]):
+        g1, g0 = tallies_dict(t1), tallies_dict(t0)
+        for k in COUNTS:
+            assert g1[k] == g0[k], (s.name, k)
+        np.testing.assert_allclose(f0, f1, rtol=1e-11, atol=1e-13, err_msg=s.name)
+        assert g0["total_flux"] == pytest.approx(g1["total_flux"], rel=1e-11)
+        assert g0["sigma_total_flux"] == pytest.approx(g1["sigma_total_flux"], rel=1e-11)
+        _print(s.name, "chunks", g1["batches"], "gathered batches", g0["batches"])
+        assert 256 <= g0["batches"] <= g1["batches"], s.name
+        assert np.array_equal(e1 > 0, e0 > 0), s.name
+        ratio = e0[e1 > 0] / e1[e1 > 0]
+        # the spread of a batch-means error is about 1 / sqrt(2 (B - 1)) where
+        # many histories reach the bin (relative error below 1%); in sparsely
+        # reached bins it is set by the few histories that score there
+        dense = (e1 > 0) & (e1 < 0.01 * np.abs(f1))
+        rd = e0[dense] / e1[dense]
+        tol = 8.0 / np.sqrt(2.0 * (g0["batches"] - 1))
+        _print(s.name, "flux sigma ratio: all bins", ratio.min(), np.median(ratio), ratio.max(), "dense bins",
+               int(dense.sum()), rd.min(), rd.max(), "tolerance", tol)
+        assert dense.sum() >= 10, s.name
+        assert np.all(np.abs(rd - 1.0) <= tol), s.name
+        assert abs(np.median(ratio) - 1.0) <= 0.05, s.name
+    n_chunks = sum(t.batches for t, _, _ in out[1])
+    n_gathered = sum(t.batches for t, _, _ in out[0])
+    _print("chunks", n_chunks, "gathered batches", n_gathered)
+    assert n_gathered <= n_chunks // 2
+
+
 def test_single_tally_buffer_mode_matches_oracle(cls):
     """A 1000-bin mesh with chunks of at least 2048 histories runs with one LDS
     tally buffer per wave (more waves resident than with two); with chunks of
     at most 1024 histories the same problem runs with two buffers. Both give
     the oracle's counts exactly (FP64 on the same streams) and its flux to
-    rounding (the chunking changes the order of the sums)."""
+    rounding (the chunking changes the order of the sums). Every chunk is its
+    own error batch here, so that the batch count shows the chunk size."""
     s = Spec(1, (0.5, 1.5), (0.5, 0.9), (1.0, 0.3), 1000, 48_000_000, 31)
     _print("single-buffer case: rod, 1000 bins, 4.8e7 histories")
     o = run_oracle(s)
     results = []
     try:
         for max_chunk in (0, 1024):
-            cls.cls_set_launch_config(0, 0, max_chunk, 0)
+            cls.cls_set_launch_config(0, 0, max_chunk, 0, chunk_batches=1)
             g, flux, _, _ = run_gpu(s)
             _print("max_chunk", max_chunk, "histories per chunk", g["histories"] / g["batches"])
             results.append((g, flux))

@@ -1,8 +1,12 @@
 """The allocation-free entry point (cls_run_static) against cls_run: two calls in a
 row on one device, the second with a smaller problem (fewer histories and bins),
-each equal to the same run through cls_run (integer tallies bitwise, FP64 sums to
-summation order); sizes beyond the static workspace are refused. All GPU calls go
-through the C ABI; the result buffer is caller-owned device memory (a torch tensor)."""
+each equal to the same run through cls_run. With every chunk its own error batch
+(chunk_batches = 1) the records are equal (integer tallies bitwise, FP64 sums to
+summation order); with the default gathering of chunks into batches, whose
+composition follows the order in which waves take chunks, the counts, means and
+per-history errors are equal and the per-bin flux errors agree statistically.
+Sizes beyond the static workspace are refused. All GPU calls go through the C ABI;
+the result buffer is caller-owned device memory (a torch tensor)."""
 from __future__ import annotations
 
 import numpy as np
@@ -14,7 +18,7 @@ from paper_1708_00765_amd.inputs import Spec
 pytestmark = pytest.mark.gpu
 
 COUNTS = ("histories", "transmitted", "reflected", "absorbed", "capped", "flights", "collisions", "scatters",
-          "interface_crossings", "lateral_reflections", "batches")
+          "interface_crossings", "lateral_reflections")
 
 
 @pytest.fixture(scope="module")
@@ -52,24 +56,44 @@ def _plain_run(cls, s, fp32):
     return tallies_dict(t), flux, fsig
 
 
+@pytest.mark.parametrize("chunk_batches", [1, 0])
 @pytest.mark.parametrize("fp32", [True, False])
-def test_static_runs_equal_cls_run(env, fp32):
+def test_static_runs_equal_cls_run(env, fp32, chunk_batches):
     torch, cls = env
     big = Spec(3, (0.6, 1.4), (0.7, 0.95), (0.8, 0.4), 1500, 3_000_000, 6101)
     small = Spec(2, (0.3, 2.0), (0.5, 0.9), (2.0, 0.2), 37, 40_000, 6102)
-    for s in (big, small):        # the second call reuses the workspace with a smaller input
-        print("static run", "fp32" if fp32 else "fp64", s.d, s.nbins, s.histories, flush=True)
-        rec, flux, fsig = _static_run(torch, cls, s, fp32)
-        ref, rflux, rfsig = _plain_run(cls, s, fp32)
-        for k in COUNTS:
-            assert rec[k] == ref[k], (k, rec[k], ref[k])
-        for k in ("T", "R", "A", "sigma_T", "sigma_R", "sigma_A"):
-            assert rec[k] == ref[k], k
-        for k in ("total_flux", "sigma_total_flux"):
-            assert abs(rec[k] - ref[k]) <= 1e-11 * abs(ref[k]), k
-        np.testing.assert_allclose(flux, rflux, rtol=1e-11, atol=1e-14)
-        np.testing.assert_allclose(fsig, rfsig, rtol=1e-8, atol=1e-14)
-        assert rec["transmitted"] + rec["reflected"] + rec["absorbed"] == s.histories
+    cls.cls_set_launch_config(chunk_batches=chunk_batches)
+    try:
+        for s in (big, small):        # the second call reuses the workspace with a smaller input
+            print("static run", "fp32" if fp32 else "fp64", "chunk_batches", chunk_batches, s.d, s.nbins,
+                  s.histories, flush=True)
+            rec, flux, fsig = _static_run(torch, cls, s, fp32)
+            ref, rflux, rfsig = _plain_run(cls, s, fp32)
+            for k in COUNTS:
+                assert rec[k] == ref[k], (k, rec[k], ref[k])
+            for k in ("T", "R", "A", "sigma_T", "sigma_R", "sigma_A"):
+                assert rec[k] == ref[k], k
+            for k in ("total_flux", "sigma_total_flux"):
+                assert abs(rec[k] - ref[k]) <= 1e-11 * abs(ref[k]), k
+            np.testing.assert_allclose(flux, rflux, rtol=1e-11, atol=1e-14)
+            if chunk_batches:
+                assert rec["batches"] == ref["batches"]
+                np.testing.assert_allclose(fsig, rfsig, rtol=1e-8, atol=1e-14)
+            else:
+                # batch-means errors from two batchings of the same histories:
+                # each has a relative spread of about 1 / sqrt(2 (B - 1))
+                b = min(rec["batches"], ref["batches"])
+                assert b >= min(256, ref["histories"] // 64)
+                ok = rfsig > 0
+                ratio = fsig[ok] / rfsig[ok]
+                tol = 8.0 / np.sqrt(2.0 * (b - 1))
+                print("batches", rec["batches"], ref["batches"], "flux sigma ratio", ratio.min(), ratio.max(),
+                      "tolerance", tol, flush=True)
+                assert np.all(np.abs(ratio - 1.0) <= tol)
+                assert np.array_equal(fsig > 0, rfsig > 0)
+            assert rec["transmitted"] + rec["reflected"] + rec["absorbed"] == s.histories
+    finally:
+        cls.cls_set_launch_config(0, 0, 0, 0)
 
 
 def test_static_run_refuses_what_does_not_fit(env):
