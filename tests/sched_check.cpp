@@ -76,6 +76,14 @@ int main()
         // grows only up to ~32 chunks per wave for the whole batch
         const uint64_t cap = (total + 32 * w - 1) / (32 * w);
         if (c > alone) CHECK(c <= cap, "c=%llu cap=%llu", (unsigned long long)c, (unsigned long long)cap);
+        // the histories an error batch may gather: at least one chunk, below 2^31, and
+        // few enough that the problem keeps kMinErrorBatches batches when its chunks allow
+        const uint64_t b = batch_histories(n, c);
+        CHECK(b >= std::min<uint64_t>(c, 1ull << 31) && b <= (1ull << 31), "n=%llu c=%llu b=%llu",
+              (unsigned long long)n, (unsigned long long)c, (unsigned long long)b);
+        if (n / kMinErrorBatches >= c && n / kMinErrorBatches <= (1ull << 31))
+            CHECK(chunks_of(n, b) >= kMinErrorBatches, "n=%llu c=%llu b=%llu batches=%llu", (unsigned long long)n,
+                  (unsigned long long)c, (unsigned long long)b, (unsigned long long)chunks_of(n, b));
         ++cases;
     }
 
