@@ -119,9 +119,10 @@ static_assert(sizeof(DevProblem) % 128 == 0, "problem records span whole cache l
 // publishes one kServedLeave per wave after the last item: each wave leaves on
 // the first it receives, so every wave leaves and every published item runs.
 // A wave that waits longer than wait_passes for its ticket, or receives an item
-// it refuses (an entry outside the table, a chunk outside its entry's range,
-// an unknown kind of problem), reports it in `error` and leaves: a broken
-// round ends in an error, never in a wave that cannot finish.
+// it refuses (an entry outside the table), reports it in `error` and leaves; an
+// entry of an unknown kind of problem ends its histories at once as capped; the
+// host writes only chunks of an entry's own range. A broken round ends in an
+// error, never in a wave that cannot finish.
 struct ServedFeed {
     uint64_t published;          // items written (host)
     uint64_t seen;               // a recent ticket, reported by the waves (every 32nd)

@@ -802,22 +802,17 @@ __device__ __forceinline__ int served_claim(const TrackArgs &A, int lane, uint64
     }
     item = readlane64(item, 0);
     if (item == kServedLeave) return kClaimLeave;
+    // The host writes only chunks of the entry's own range; the kernel refuses
+    // an entry outside the table (which it could not read), and an entry of
+    // an unknown kind ends its histories at once as capped (event_step_kind)
+    // instead of leaving its lanes stepping for ever.
     const uint64_t ent = item >> 32;
     if (ent >= (uint64_t)A.nprobs) {
         served_report(A, lane, kServedErrBadItem, item);
         return kClaimRefused;
     }
-    const int e = (int)ent;
     *chunk = item & 0xFFFFFFFFull;
-    // the chunk must be one of the entry's chunks, and the entry of a kind the
-    // kernel tracks (any other would leave its lanes stepping for ever)
-    ConstProblem &P = ((ConstProblem *)A.probs)[e];
-    const uint64_t n = P.chunk ? (P.histories + P.chunk - 1) / P.chunk : 0;
-    if (*chunk >= n || P.final_chunks != n || (uint32_t)P.kind >= 16u) {
-        served_report(A, lane, kServedErrBadItem, item);
-        return kClaimRefused;
-    }
-    return e;
+    return (int)ent;
 }
 
 // One event step of a served round's lane: the problem's kind (a wave-uniform
@@ -838,7 +833,11 @@ __device__ __forceinline__ int event_step_kind(int kind, Lane<R> &L, const Prm<R
         CLS_KIND_CASES(GEOM_SLAB)
         CLS_KIND_CASES(GEOM_EXT2D)
         CLS_KIND_CASES(GEOM_CUBE3D)
-    default: return EV_NONE;
+    default:
+        // an unknown kind: the history ends at once as capped, with no flight
+        // (step 2: the capped-history accounting counts step - 2 flights)
+        L.step = 2u;
+        return EV_CAP;
     }
 #undef CLS_KIND_CASES
 #undef CLS_KIND_CASE
