@@ -15,7 +15,7 @@
 //    layers in LDS (cell gaps and colours drawn 64 at a time, one cell per lane,
 //    then summed in cell order exactly like a sequential walk from x = 0), and
 //    transports the realization's N histories with one history per lane and
-//    lane refill;
+//    lane refill once at least kQRefillMin lanes are idle;
 //  * the slab needs FP64 here: the run reproduces the FP64 oracle's streams
 //    (cell i of realization k: Philox block (i, 3, k); step j of history
 //    g = kN + h: block (j, 2, g)); distances are taken as products with 1 /
@@ -98,6 +98,11 @@ __device__ __forceinline__ void q_track(double *tal, double xa, double xb, doubl
     atomicAdd(tal + kb + 1, -pb);
 }
 
+// Idle lanes a wave waits for before it hands out new histories (or the whole
+// wave idle): a history's first step (the source) is a branch beside the
+// flights, which a refill of a single lane runs with one lane active.
+constexpr uint32_t kQRefillMin = 8;
+
 template <bool SLAB, int SRC, int EST>
 __global__ void __launch_bounds__(256) quenched_kernel(const DevQuenched *rec)
 {
@@ -174,7 +179,7 @@ __global__ void __launch_bounds__(256) quenched_kernel(const DevQuenched *rec)
 
         for (;;) {
             uint64_t dead = q_ballot(!alive);
-            if (dead != 0 && next < N) {
+            if (dead != 0 && next < N && (dead == ~0ull || (uint32_t)__popcll(dead) >= kQRefillMin)) {
                 const uint64_t avail = N - next;
                 const uint32_t nd = (uint32_t)__popcll(dead);
                 const uint32_t take = avail < nd ? (uint32_t)avail : nd;
