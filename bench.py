@@ -415,9 +415,17 @@ def _latency_stages(infos):
     return out
 
 
+# Served requests kept for the comparison with the FP64 oracle (in the CPU
+# baseline leg): the first ones of at most this many histories.
+SERVED_ORACLE_SAMPLE = 16
+SERVED_ORACLE_MAX_HISTORIES = 200_000
+
+
 def run_served(cls, seconds, rate):
     """Submit the served workload's Poisson stream in real time; latency is
-    arrival to results on the host, measured by the server's clock."""
+    arrival to results on the host, measured by the server's clock. Also keeps
+    the results of a bounded sample of small requests (key `_oracle_sample`, not
+    reported) for the comparison with the oracle."""
     from paper_1708_00765_amd.inputs import served_requests
     import numpy as np
     reqs = served_requests(rate_hz=rate, duration_s=seconds)
@@ -439,6 +447,8 @@ def run_served(cls, seconds, rate):
         _wait_all(cls, srv, [tk for tk, _, _ in live], "served")
         infos = [cls.cls_server_request_info(srv, tk) for tk, _, _ in live]
         stats = cls.cls_server_get_stats(srv)
+        sample = [(s, cls.cls_read_tallies(p, s.nbins)) for _, p, s in live
+                  if s.histories <= SERVED_ORACLE_MAX_HISTORIES][:SERVED_ORACLE_SAMPLE]
     finally:
         cls.cls_server_destroy(srv)
         for _, p, _ in live:
@@ -454,7 +464,7 @@ def run_served(cls, seconds, rate):
             "max_ms": float(lat.max()), "histories": hist, "histories_per_s": hist / (last - first),
             "offered_histories_per_s": hist / seconds, "rounds": stats["rounds"],
             "wave_idle_share": stats["wave_idle_share"],
-            "hbm_peak_bytes": stats["hbm_peak"], "latency_stages_ms": stages,
+            "hbm_peak_bytes": stats["hbm_peak"], "latency_stages_ms": stages, "_oracle_sample": sample,
             "workload": "served: d uniform in {1 (rod, collision flux), 2 (ext2d), 3 (cube3d)}, "
                         "histories log-uniform in [1e4, 1e8], 10-1000 bins, FP32 tracking"}
 
@@ -803,6 +813,19 @@ def main() -> int:
         log(f"fp32 batched vs the FP64 oracle ({n_each} histories per set): max |z| {oracle_vs['max_abs_z_scalars']:.2f}, "
             f"bins beyond 4 sigma {oracle_vs['bins_beyond_4_sigma']} of {oracle_vs['bins']} "
             f"(allowed {oracle_vs['bins_beyond_4_sigma_allowed']})")
+        # served requests (FP32) against oracle runs of the same requests on independent streams
+        if served and served.get("_oracle_sample"):
+            sample = served["_oracle_sample"]
+            orc_s = [run_oracle(s, seed=s.seed ^ 0x5DEECE66D) for s, _ in sample]
+            sv = oracle_agreement([t for _, t in sample], orc_s)
+            sv.pop("oracle_histories_per_set", None)
+            sv["requests"] = len(sample)
+            sv["sample"] = (f"the first {len(sample)} served requests of at most {SERVED_ORACLE_MAX_HISTORIES} "
+                            "histories, each against the FP64 oracle on independent streams")
+            served["fp32_vs_oracle"] = sv
+            log(f"served vs the FP64 oracle ({len(sample)} requests): max |z| {sv['max_abs_z_scalars']:.2f}, "
+                f"bins beyond 4 sigma {sv['bins_beyond_4_sigma']} of {sv['bins']} "
+                f"(allowed {sv['bins_beyond_4_sigma_allowed']})")
 
     traffic = measured_traffic(args.workload) if not args.histories else None
     kernel_ms = main_leg["kernel_ms"]
@@ -839,7 +862,7 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "cube3d_track": cube,
-        "served": served,
+        "served": {k: v for k, v in served.items() if not k.startswith("_")} if served else None,
         "served_saturated": served_sat,
         "ext2d_batched_vs_fp64_plain": ext2d,
         "paper_rows": paper,
