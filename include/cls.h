@@ -147,7 +147,7 @@ cls_status cls_synchronize(cls_problem *p);
 typedef struct {
     uint64_t histories, transmitted, reflected, absorbed, capped;
     uint64_t flights, collisions, scatters, interface_crossings, lateral_reflections;
-    uint64_t batches;            /* history chunks used for the batch-means flux error */
+    uint64_t batches;            /* batches of the batch-means flux error               */
     double T, R, A;              /* per source history                                 */
     double sigma_T, sigma_R, sigma_A;
     double total_flux;           /* sum_k flux_k * dx: mean flux score per history     */
@@ -157,9 +157,12 @@ typedef struct {
 
 /* Copy the results of the last completed run. flux and flux_sigma (nbins doubles
  * each, may be NULL) receive the bin-averaged scalar flux per history and its
- * batch-means one-sigma error; nbins must equal the problem's mesh size.
- * The event counts (flights, collisions, scatters, crossings, reflections) are
- * summed per work chunk in 32 bits before they reach these 64-bit totals, so a
+ * batch-means one-sigma error (batches of n_b histories with bin scores s_b:
+ * sigma^2 = sum (s_b - n_b m)^2 / (N - sum n_b^2 / N) per history, unbiased for
+ * any batch sizes; the error of the mean is sqrt(sigma^2 / N)); nbins must
+ * equal the problem's mesh size. The event counts (flights, scatters,
+ * crossings) are summed per lane and work chunk in 32 bits before they reach
+ * these 64-bit totals, so a
  * history is cut (counted in `capped`, CLS_ERR_EVENT_CAP) after
  * min(10^8, floor((2^32 - 1) / histories per chunk)) flights: 2.6e5 flights
  * with the default max_chunk of 16384, 65535 with chunks of 65536 histories
@@ -185,11 +188,12 @@ cls_status cls_read_trace(const cls_problem *p, uint64_t *hash, uint32_t *flight
  * otherwise); histories[i] and seeds[i] belong to problems[i]. Every problem
  * receives the same tallies it would get from cls_run with the same histories
  * and seed (counts exactly, FP64 sums up to the order of additions) except
- * flux_sigma: the per-bin error is a batch-means estimate over the work
- * chunks, and in a batch a problem's chunks may be larger (sized for the whole
- * batch, at least 256 of them per problem when its history count allows), so
- * flux_sigma is an equally valid estimate from other batches. The same holds
- * for a different launch configuration. The launch uses the stream of
+ * flux_sigma and the batch count: the per-bin error is a batch-means estimate,
+ * and a batch gathers the chunks one wave takes of a problem (chunk_batches in
+ * cls_launch_config), with chunks sized for the whole batch, at least 256
+ * batches per problem when its history count allows; flux_sigma is then an
+ * equally valid estimate from other batches. The same holds for a different
+ * launch configuration or another run. The launch uses the stream of
  * problems[0] and is synchronous. */
 cls_status cls_run_batch(cls_problem *const *problems, const uint64_t *histories,
                          const uint64_t *seeds, int n);
@@ -251,8 +255,8 @@ cls_status cls_get_launch_config(cls_launch_config *cfg);
  * would run for `problems` and `histories` (same rules): the first chunks of
  * every problem, cut as in the whole batch. The search runs in two stages:
  * LDS tally buffers per wave (automatic, 1, 2) x workgroup size (automatic, 2,
- * 4, 8 waves), then, for the fastest, chunk size (4096, 16384, 65536; the chunk
- * is also the error batch) x refill threshold (1, 4, 16). Makes the fastest shape the
+ * 4, 8 waves), then, for the fastest, chunk size (4096, 16384, 65536) x refill
+ * threshold (1, 4, 16); chunk_batches stays as set. Makes the fastest shape the
  * process-wide launch configuration and returns it
  * in *best (and its rate in histories/s in *best_rate, 0 when it came from the
  * cache). When the environment variable CLS_AUTOTUNE_CACHE names a file,
@@ -291,7 +295,7 @@ cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories,
  * signals the worker, which launches a finalize kernel for it while the round
  * goes on. Each result is the one cls_run would give for the same problem,
  * histories and seed (integer tallies bitwise, FP64 sums up to atomic
- * ordering). A device-side protocol error (a chunk the kernel refuses, a wave
+ * ordering). A device-side protocol error (an item the kernel refuses, a wave
  * that waited too long for its work, or a request whose chunks all ran without
  * a completion signal) fails every unfinished request and stops the server
  * (worker_status is set; later submissions fail with CLS_ERR_STATE). */
