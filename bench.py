@@ -633,7 +633,7 @@ def main() -> int:
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed passes of the FP64 plain leg (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=30.0, help="oracle sample budget (0 = skip)")
     ap.add_argument("--max-chunk", type=int, default=0,
-                    help="histories per work chunk (= error batch) of the main workload's FP32 launches "
+                    help="histories per work chunk of the main workload's FP32 launches "
                          "(0: the launch configuration's; implies --autotune 0)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: the main workload's FP32 launches use the autotuned configuration "
