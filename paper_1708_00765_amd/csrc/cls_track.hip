@@ -290,8 +290,7 @@ __device__ __forceinline__ int event_step(Lane<R> &L, const Prm<R> &P, double *t
         L.x = 0.0; L.dy = 0; L.dz = 0;
         L.uy = (R)-1; L.uz = (R)-1;
         // the chord factor is 1 on the rod and in the cube (the slab and the
-        // extruded geometry set theirs below); set here because a served
-        // round's lane may have run a history of another geometry before
+        // extruded geometry set theirs below)
         if (G == GEOM_ROD || G == GEOM_CUBE3D) L.ig = (R)1;
         if (SRC == SRC_FACE) {
             if (G == GEOM_ROD) {
@@ -804,8 +803,8 @@ __device__ __forceinline__ int served_claim(const TrackArgs &A, int lane, uint64
     if (item == kServedLeave) return kClaimLeave;
     // The host writes only chunks of the entry's own range; the kernel refuses
     // an entry outside the table (which it could not read), and an entry of
-    // an unknown kind ends its histories at once as capped (event_step_kind)
-    // instead of leaving its lanes stepping for ever.
+    // an unknown kind ends its histories at once as capped (the loop of
+    // kKindUnknown) instead of leaving its lanes stepping for ever.
     const uint64_t ent = item >> 32;
     if (ent >= (uint64_t)A.nprobs) {
         served_report(A, lane, kServedErrBadItem, item);
@@ -813,34 +812,6 @@ __device__ __forceinline__ int served_claim(const TrackArgs &A, int lane, uint64
     }
     *chunk = item & 0xFFFFFFFFull;
     return (int)ent;
-}
-
-// One event step of a served round's lane: the problem's kind (a wave-uniform
-// value) selects the geometry, estimator and source.
-template <bool FP32, typename R>
-__device__ __forceinline__ int event_step_kind(int kind, Lane<R> &L, const Prm<R> &P, double *tal,
-                                               const MatRow<R> *mtab)
-{
-#define CLS_KIND_CASE(g, e, s) \
-    case problem_kind(g, e, s): return event_step<g, e, s, FP32, false, R>(L, P, tal, mtab);
-#define CLS_KIND_CASES(g)                          \
-    CLS_KIND_CASE(g, EST_COLLISION, SRC_FACE)      \
-    CLS_KIND_CASE(g, EST_COLLISION, SRC_VOLUME)    \
-    CLS_KIND_CASE(g, EST_TRACK, SRC_FACE)          \
-    CLS_KIND_CASE(g, EST_TRACK, SRC_VOLUME)
-    switch (kind) {
-        CLS_KIND_CASES(GEOM_ROD)
-        CLS_KIND_CASES(GEOM_SLAB)
-        CLS_KIND_CASES(GEOM_EXT2D)
-        CLS_KIND_CASES(GEOM_CUBE3D)
-    default:
-        // an unknown kind: the history ends at once as capped, with no flight
-        // (step 2: the capped-history accounting counts step - 2 flights)
-        L.step = 2u;
-        return EV_CAP;
-    }
-#undef CLS_KIND_CASES
-#undef CLS_KIND_CASE
 }
 
 // ---------------------------------------------------------------------------
@@ -916,26 +887,56 @@ __device__ __forceinline__ void flush_any(SlotState &S, const TrackArgs &A, doub
 // ---------------------------------------------------------------------------
 // the tracking kernel
 // ---------------------------------------------------------------------------
+// A wave's LDS area: one or two tally buffers of KP doubles, then the score
+// sum and score square sum of each slot, then kSlotCounters 64-bit counter
+// words per slot, then the material rows of each slot, then (served rounds)
+// the wave's claim state.
+__device__ __forceinline__ double *wave_lds(const TrackArgs &A, int wid)
+{
+    extern __shared__ double lds[];
+    return lds + (size_t)wid * ((size_t)A.slots * (size_t)A.lds_stride + kWaveExtraDoubles);
+}
+__device__ __forceinline__ double *wave_sums(const TrackArgs &A, double *wbuf) { return wbuf + A.slots * A.lds_stride; }
+__device__ __forceinline__ uint64_t *wave_ctrs(const TrackArgs &A, double *wbuf)
+{
+    return (uint64_t *)(wave_sums(A, wbuf) + 4);                       // [slot][kSlotCounters]
+}
+__device__ __forceinline__ uint64_t *wave_served(const TrackArgs &A, double *wbuf)
+{
+    return (uint64_t *)(wave_sums(A, wbuf) + 4 + 2 * kSlotCounters + kMatTableDoubles);
+}
+
+// Kinds of problem a served round's kernel has a tracking loop for (every
+// geometry, estimator and source); another value ends its histories at once.
+constexpr int kKinds = 16;
+constexpr int kKindUnknown = -2;   // the G of the loop for kinds outside [0, kKinds)
+static_assert(problem_kind(GEOM_CUBE3D, EST_TRACK, SRC_VOLUME) == kKinds - 1, "kinds are 0 .. kKinds - 1");
+
+// The tracking loop of a wave. A batch launch runs it once for the launch's
+// kind of problem. A served round runs the loop of the kind of the chunk it
+// holds: when the wave takes a chunk of another kind, the chunk waits in the
+// wave's W_PEND word, the loop runs its histories out and returns true, and the
+// round's kernel enters the loop of that kind (returns false once the wave
+// leaves the round). Every kind has its own loop, so each is compiled and
+// register-allocated for its geometry, estimator and source alone.
 template <int G, int EST, int SRC, bool FP32, bool TRACE, bool SERVED>
-__device__ __forceinline__ void track_loop(const TrackArgs &A)
+__device__ __forceinline__ bool track_loop(const TrackArgs &A)
 {
     using R = typename std::conditional<FP32, float, double>::type;
 
-    extern __shared__ double lds[];
     const int lane = (int)(threadIdx.x & 63u);
     const int wid = (int)(threadIdx.x >> 6);
     const int KP = A.lds_stride;
     const int nslots = A.slots;
-    // per wave: one or two tally buffers of KP doubles, then the score sum and
-    // score square sum of each slot, then kSlotCounters 32-bit counters per
-    // slot, then the material rows of each slot, then (served rounds) the
-    // wave's claim state
-    double *const wbuf = lds + (size_t)wid * ((size_t)nslots * (size_t)KP + kWaveExtraDoubles);
-    double *const wsum = wbuf + nslots * KP;
-    uint64_t *const wctr = (uint64_t *)(wsum + 4);    // [slot][kSlotCounters]
+    double *const wbuf = wave_lds(A, wid);
+    double *const wsum = wave_sums(A, wbuf);
+    uint64_t *const wctr = wave_ctrs(A, wbuf);
     MatRow<R> *const wmat = (MatRow<R> *)(wsum + 4 + 2 * kSlotCounters);   // [slot][material]
-    uint64_t *const wsrv = (uint64_t *)(wsum + 4 + 2 * kSlotCounters + kMatTableDoubles);
-    for (int i = lane; i < nslots * KP + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
+    uint64_t *const wsrv = wave_served(A, wbuf);
+    // (a served wave's area is cleared once, by its kernel: a loop starts and
+    // ends with every slot flushed, which leaves the slots' words zero)
+    if constexpr (!SERVED)
+        for (int i = lane; i < nslots * KP + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
 
     // Wave-uniform state of the two slots, kept as two named records (never
     // indexed by a run-time value, so that they stay in scalar registers): C
@@ -974,11 +975,6 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
     // SV_WAITED counts those passes since the ticket was taken. The device
     // clock is read only where an idle stretch begins and ends.
     bool idle_stretch = false;
-    if (SERVED && lane == 0) {
-        wsrv[SV_TICKET] = kNoTicket;
-        wsrv[SV_POLL_GAP] = 1;
-        wsrv[SV_BORN] = wall_clock64();
-    }
 
     Lane<R> L;
     L.x = 0.0; L.dy = L.dz = L.ux = L.uy = L.uz = 0;
@@ -1003,8 +999,14 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
                 if (slot_free && !queue_empty) {
                     uint64_t chunk_index = 0;
                     int lo = kClaimWait;
+                    const uint64_t pend = lds_uniform(wctr + W_PEND);
                     const uint64_t poll_wait = lds_uniform(wsrv + SV_POLL_WAIT);
-                    if (poll_wait == 0) {
+                    if (pend != kNoChunk) {
+                        // the chunk that made the wave enter this loop
+                        lo = (int)(pend >> 32);
+                        chunk_index = pend & 0xFFFFFFFFull;
+                        if (lane == 0) wctr[W_PEND] = kNoChunk;
+                    } else if (poll_wait == 0) {
                         lo = served_claim(A, lane, wsrv, &chunk_index);
                         const uint64_t gap = lds_uniform(wsrv + SV_POLL_GAP);
                         if (lane == 0) {
@@ -1019,6 +1021,18 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
                         if (lo == kClaimLeave || lo == kClaimRefused) queue_empty = true;
                     } else if (lane == 0) {
                         wsrv[SV_POLL_WAIT] = poll_wait - 1;
+                    }
+                    if (lo >= 0) {
+                        const int kind = ((ConstProblem *)A.probs)[lo].kind;
+                        const bool other = G == kKindUnknown ? (kind >= 0 && kind < kKinds)
+                                                             : kind != problem_kind(G, EST, SRC);
+                        // a chunk for another kind's loop waits in W_PEND, and
+                        // the wave leaves this loop as if the round were over
+                        // for it (written with selects: a branch here costs the
+                        // loop ~27 more VGPRs)
+                        if (lane == 0) wctr[W_PEND] = other ? ((uint64_t)lo << 32) | chunk_index : kNoChunk;
+                        queue_empty = queue_empty || other;
+                        lo = other ? kClaimWait : lo;
                     }
                     if (lo >= 0) {
                         ConstProblem &P = ((ConstProblem *)A.probs)[lo];
@@ -1153,10 +1167,15 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
                 ConstProblem *cprob = (ConstProblem *)A.probs;
                 const Prm<R> P = load_prm<R>(cprob[pidc]);
                 double *tal = wbuf + (L.slot ? KP : 0);
-                if constexpr (G >= 0)
+                if constexpr (G >= 0) {
                     ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, tal, wmat + 2 * L.slot);
-                else
-                    ev = event_step_kind<FP32, R>(cprob[pidc].kind, L, P, tal, wmat + 2 * L.slot);
+                } else {
+                    // a kind the kernel has no loop for: the history ends at
+                    // once as capped, with no flight (step 2: the capped-history
+                    // accounting counts step - 2 flights)
+                    L.step = 2u;
+                    ev = EV_CAP;
+                }
             }
             todo &= ~ballot(mine);
         }
@@ -1203,13 +1222,8 @@ __device__ __forceinline__ void track_loop(const TrackArgs &A)
             }
         }
     }
-    if (SERVED && lane == 0) {
-        const uint64_t now = wall_clock64();
-        uint64_t idle = wsrv[SV_IDLE_TICKS];
-        if (idle_stretch) idle += now - wsrv[SV_IDLE_FROM];
-        atomicAdd(&A.served->alive_ticks, (unsigned long long)(now - wsrv[SV_BORN]));
-        atomicAdd(&A.served->idle_ticks, (unsigned long long)idle);
-    }
+    if (SERVED && idle_stretch && lane == 0) wsrv[SV_IDLE_TICKS] += (uint64_t)wall_clock64() - wsrv[SV_IDLE_FROM];
+    return SERVED && lds_uniform(wctr + W_PEND) != kNoChunk;
 }
 
 // A batch launch: one kernel per kind of problem and precision.
@@ -1219,11 +1233,51 @@ __global__ void __launch_bounds__(512) track_kernel(TrackArgs A)
     track_loop<G, EST, SRC, FP32, TRACE, false>(A);
 }
 
-// A served round: every kind of problem of one precision.
+// A served round: every kind of problem of one precision, each in its own
+// tracking loop (a wave starts in the cube's, the loop of the first chunk it
+// takes if that is another kind).
 template <bool FP32>
 __global__ void __launch_bounds__(512) served_kernel(TrackArgs A)
 {
-    track_loop<GEOM_ANY, -1, -1, FP32, false, true>(A);
+    const int lane = (int)(threadIdx.x & 63u);
+    double *const wbuf = wave_lds(A, (int)(threadIdx.x >> 6));
+    uint64_t *const wctr = wave_ctrs(A, wbuf);
+    uint64_t *const wsrv = wave_served(A, wbuf);
+    for (int i = lane; i < A.slots * A.lds_stride + kWaveExtraDoubles; i += 64) wbuf[i] = 0.0;
+    if (lane == 0) {
+        wctr[W_PEND] = kNoChunk;
+        wsrv[SV_TICKET] = kNoTicket;
+        wsrv[SV_POLL_GAP] = 1;
+        wsrv[SV_BORN] = wall_clock64();
+    }
+    int kind = problem_kind(GEOM_CUBE3D, EST_TRACK, SRC_FACE);
+    for (;;) {
+        bool more;
+#define CLS_KIND_CASE(g, e, s) \
+    case problem_kind(g, e, s): more = track_loop<g, e, s, FP32, false, true>(A); break;
+#define CLS_KIND_CASES(g)                          \
+    CLS_KIND_CASE(g, EST_COLLISION, SRC_FACE)      \
+    CLS_KIND_CASE(g, EST_COLLISION, SRC_VOLUME)    \
+    CLS_KIND_CASE(g, EST_TRACK, SRC_FACE)          \
+    CLS_KIND_CASE(g, EST_TRACK, SRC_VOLUME)
+        switch (kind) {
+            CLS_KIND_CASES(GEOM_ROD)
+            CLS_KIND_CASES(GEOM_SLAB)
+            CLS_KIND_CASES(GEOM_EXT2D)
+            CLS_KIND_CASES(GEOM_CUBE3D)
+        default: more = track_loop<kKindUnknown, EST_COLLISION, SRC_FACE, FP32, false, true>(A); break;
+        }
+#undef CLS_KIND_CASES
+#undef CLS_KIND_CASE
+        if (!more) break;
+        const uint64_t pend = lds_uniform(wctr + W_PEND);
+        kind = ((ConstProblem *)A.probs)[pend >> 32].kind;
+    }
+    if (lane == 0) {
+        const uint64_t now = wall_clock64();
+        atomicAdd(&A.served->alive_ticks, (unsigned long long)(now - wsrv[SV_BORN]));
+        atomicAdd(&A.served->idle_ticks, (unsigned long long)wsrv[SV_IDLE_TICKS]);
+    }
 }
 
 // ---------------------------------------------------------------------------
