@@ -331,7 +331,10 @@ def _span(values):
 
 def run_ext2d_comparison(cls, torch, stream, steps):
     """The 256 uneven ext2d sets (1e4..1e7 histories, 100..1000 bins): one batched
-    FP32 persistent launch per pass vs one plain FP64 launch per set."""
+    FP32 persistent launch per pass vs one plain FP64 launch per set, and the
+    batched launch's VALU roofline (its kernel time from the library's events on
+    the launch stream)."""
+    from paper_1708_00765_amd import perf_model
     from paper_1708_00765_amd.inputs import workload
     specs = workload("ext2d_batched")
     total = sum(s.histories for s in specs)
@@ -341,13 +344,18 @@ def run_ext2d_comparison(cls, torch, stream, steps):
     try:
         for p in p32 + p64:
             cls.cls_set_stream(p, stream)
+        kernel_ms = []
+
         def time_batched():
             cls.cls_run_batch(p32, hist, [s.seed for s in specs])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
+            ms = 0.0
             for k in range(steps):
                 cls.cls_run_batch(p32, hist, [s.seed + k + 1 for s in specs])
+                ms += cls.cls_read_tallies(p32[0], specs[0].nbins)[0].track_ms
             torch.cuda.synchronize()
+            kernel_ms.append(ms / steps)
             return (time.perf_counter() - t0) / steps
 
         # default launch configuration, then the autotuner's choice for these sets
@@ -375,10 +383,20 @@ def run_ext2d_comparison(cls, torch, stream, steps):
     finally:
         for p in p32 + p64:
             cls.cls_destroy_problem(p)
+    tallies = [f[0] for f in full32]
+    slots = perf_model.algorithmic_slots("ext2d", total, sum(t.flights for t in tallies),
+                                         sum(t.scatters for t in tallies),
+                                         sum(t.lateral_reflections for t in tallies), fp32=True, track=True)
+    k_ms = kernel_ms[1]                       # the tuned configuration's passes
+    achieved = slots / (k_ms * 1e-3) / 1e12
+    peak = perf_model.PEAK_SLOTS_PER_S / 1e12
     return {"sets": len(specs), "histories": total, "fp32_batched_value": total / w32,
             "fp64_plain_value": total / w64, "ratio": w64 / w32, "fp32_batched_ms": 1e3 * w32,
             "fp64_plain_ms": 1e3 * w64, "unit": "histories/s", "autotuned_config": cfg,
             "fp32_batched_default_config_value": total / w_default,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s",
+                         "frac": achieved / peak, "kernel_ms": k_ms, "algorithmic_slots_per_launch": slots,
+                         "flights_per_history": sum(t.flights for t in tallies) / total},
             "fp32_vs_fp64_same_streams": fp32_acceptance(full32, full64)}
 
 
@@ -707,7 +725,8 @@ def main() -> int:
         log(f"ext2d 256 sets: fp32 batched {ext2d['fp32_batched_value']:.4g} hist/s (autotuned "
             f"{ext2d['autotuned_config']}; default configuration "
             f"{ext2d['fp32_batched_default_config_value']:.4g}), fp64 plain "
-            f"{ext2d['fp64_plain_value']:.4g} hist/s, ratio {ext2d['ratio']:.2f}")
+            f"{ext2d['fp64_plain_value']:.4g} hist/s, ratio {ext2d['ratio']:.2f}, "
+            f"roofline frac {ext2d['roofline']['frac']:.3f}")
 
     # ---- quenched d = 1 reference kernel -------------------------------------------
     quenched = None

@@ -248,7 +248,6 @@ struct Lane {
     uint32_t n_int, n_scat, n_fl;   // interface crossings, scatters, flights (of finished histories)
     uint32_t n_t, n_r, n_a, n_cap;
     int m, slot, kcur;       // material, chunk slot (its problem and LDS buffer), bin of x
-    bool alive;
 };
 
 // Flux bin of x and, in FP32, the position of x inside that bin in bin
@@ -887,6 +886,20 @@ __device__ __forceinline__ void flush_any(SlotState &S, const TrackArgs &A, doub
 // ---------------------------------------------------------------------------
 // the tracking kernel
 // ---------------------------------------------------------------------------
+// One event step of a lane with the loop's kind of problem; the loop for
+// kinds outside [0, kKinds) ends the history at once as capped, with no flight
+// (step 2: the capped-history accounting counts step - 2 flights).
+template <int G, int EST, int SRC, bool FP32, bool TRACE, typename R>
+__device__ __forceinline__ int lane_step(Lane<R> &L, const Prm<R> &P, double *tal, const MatRow<R> *mtab)
+{
+    if constexpr (G >= 0) {
+        return event_step<G, EST, SRC, FP32, TRACE, R>(L, P, tal, mtab);
+    } else {
+        L.step = 2u;
+        return EV_CAP;
+    }
+}
+
 // A wave's LDS area: one or two tally buffers of KP doubles, then the score
 // sum and score square sum of each slot, then kSlotCounters 64-bit counter
 // words per slot, then the material rows of each slot, then (served rounds)
@@ -982,7 +995,10 @@ __device__ __forceinline__ bool track_loop(const TrackArgs &A)
     L.tscore = 0.0; L.ssum = 0.0; L.ssq = 0.0; L.h = 0; L.hash = 0; L.step = 0;
     L.n_int = L.n_scat = L.n_fl = 0;
     L.n_t = L.n_r = L.n_a = L.n_cap = 0;
-    L.m = 0; L.slot = 0; L.kcur = 0; L.alive = false;
+    L.m = 0; L.slot = 0; L.kcur = 0;
+    // the lanes with a history in flight, as a wave mask (a lane reads its bit
+    // with no VALU work)
+    uint64_t live = 0;
 
     for (;;) {
         // ---------------- hand out histories to idle lanes ----------------
@@ -991,7 +1007,7 @@ __device__ __forceinline__ bool track_loop(const TrackArgs &A)
         // At most one hand-out per step: when the current chunk runs out, a
         // new one is claimed first (if the other slot is free); idle lanes the
         // chunk cannot serve wait for the next step.
-        uint64_t dead = ballot(!L.alive);
+        uint64_t dead = ~live;
         if (dead != 0 && (dead == ~0ull || popc(dead) >= (uint32_t)A.refill_min)) {
             if constexpr (SERVED) {
                 // a served round: every chunk is a batch of its own
@@ -1109,7 +1125,7 @@ __device__ __forceinline__ bool track_loop(const TrackArgs &A)
                 // the r-th idle lane takes history C.h0 + C.next + r (an
                 // exec-masked block: scalar values move straight into the
                 // lanes' registers, where selects would first copy them)
-                const bool nw = !L.alive && r < take;
+                const bool nw = __builtin_amdgcn_inverse_ballot_w64(dead) && r < take;
                 if (nw) {
                     // sums of the lane's histories in the other slot, or of an
                     // earlier chunk of this slot's batch, go to the slot first
@@ -1119,11 +1135,11 @@ __device__ __forceinline__ bool track_loop(const TrackArgs &A)
                     L.step = 0u;
                     L.tscore = 0.0;
                     if (TRACE) L.hash = 0xCBF29CE484222325ull;
-                    L.alive = true;
                 }
+                live |= ballot(nw);
                 C.next += take;
                 C.live += take;
-                dead = ballot(!L.alive);
+                dead = ~live;
             }
         }
 
@@ -1157,27 +1173,21 @@ __device__ __forceinline__ bool track_loop(const TrackArgs &A)
         // its parameters in scalars, both slots at once when they hold the
         // same problem.
         int ev = EV_NONE;
-        uint64_t todo = ballot(L.alive);
+        uint64_t todo = live;
         const bool same = C.open && O.open && C.pid == O.pid;
         while (todo != 0) {
             const int sc = __builtin_amdgcn_readlane(L.slot, __builtin_ctzll(todo));
             const int pidc = sc == cp ? C.pid : O.pid;
-            const bool mine = L.alive && ((todo >> lane) & 1ull) && (same || L.slot == sc);
-            if (mine) {
+            // this pass's lanes as a wave mask (a lane takes its bit of it
+            // with no VALU work): the live lanes of slot sc, or of both slots
+            // when they hold the same problem
+            const uint64_t pass = same ? todo : todo & ballot(L.slot == sc);
+            if (__builtin_amdgcn_inverse_ballot_w64(pass)) {
                 ConstProblem *cprob = (ConstProblem *)A.probs;
                 const Prm<R> P = load_prm<R>(cprob[pidc]);
-                double *tal = wbuf + (L.slot ? KP : 0);
-                if constexpr (G >= 0) {
-                    ev = event_step<G, EST, SRC, FP32, TRACE, R>(L, P, tal, wmat + 2 * L.slot);
-                } else {
-                    // a kind the kernel has no loop for: the history ends at
-                    // once as capped, with no flight (step 2: the capped-history
-                    // accounting counts step - 2 flights)
-                    L.step = 2u;
-                    ev = EV_CAP;
-                }
+                ev = lane_step<G, EST, SRC, FP32, TRACE, R>(L, P, wbuf + (L.slot ? KP : 0), wmat + 2 * L.slot);
             }
-            todo &= ~ballot(mine);
+            todo &= ~pass;
         }
 
         // ---------------- histories that ended -------------------------------
@@ -1205,8 +1215,8 @@ __device__ __forceinline__ bool track_loop(const TrackArgs &A)
                         P.trace_len[L.h] = L.step - 1u - (ev == EV_CAP ? 1u : 0u);
                     }
                 }
-                L.alive = false;
             }
+            live &= ~m_fin;
 
             // ------------- flush batches whose last history ended ------------
             // (every lane that ran histories of the batch is idle now and holds
