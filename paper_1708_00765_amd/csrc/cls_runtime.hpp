@@ -84,6 +84,7 @@ uint64_t trace_count(const cls_problem *p, uint64_t histories);
 using sched::batch_chunk_size;
 using sched::chunk_size;
 using sched::grouped_chunk_size;
+using sched::served_chunk_size;
 uint32_t unit_threshold(double q);
 // The device record of a run of p; every chunk is its own error batch
 // (batch_max = chunk) until the caller sets batch_max (batch_limit).

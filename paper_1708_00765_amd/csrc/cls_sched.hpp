@@ -58,6 +58,27 @@ inline uint64_t grouped_chunk_size(uint64_t n, uint64_t waves_total, uint64_t ma
     return std::max(c, std::min(std::min(cap, c_err), max_chunk));
 }
 
+// A served request's chunk: the rule above with chunks up to one wave's share
+// of a round; a request with at least that share for every wave of the round
+// is cut into a whole number of chunks per wave (the count nearest to n /
+// (waves x share), more if max_chunk needs it; chunks of 64 histories or
+// more, and at least kMinErrorBatches of them), so that run alone it ends on
+// every wave at about the same time instead of leaving most waves idle while
+// some run one chunk more.
+inline uint64_t served_chunk_size(uint64_t n, uint64_t waves_total, uint64_t max_chunk, uint64_t share)
+{
+    const uint64_t c = grouped_chunk_size(n, waves_total, max_chunk, share);
+    const uint64_t w = std::max<uint64_t>(waves_total, 1);
+    const uint64_t per = std::min(share, max_chunk);
+    if (per < 64 || n / w < per) return c;
+    uint64_t k = (n + w * per / 2) / (w * per);                       // nearest whole number
+    k = std::max<uint64_t>(k, (n + w * max_chunk - 1) / (w * max_chunk));
+    k = std::max<uint64_t>(k, 1);
+    const uint64_t b = std::min<uint64_t>((n + k * w - 1) / (k * w), max_chunk);
+    // (the error batches: a request keeps kMinErrorBatches chunks)
+    return (n + b - 1) / b >= std::min<uint64_t>(kMinErrorBatches, n) ? b : c;
+}
+
 // Histories of a problem of n histories, cut into chunks of `chunk`, that
 // one error batch may gather (a wave adds the chunks it takes of the problem
 // to its batch while they fit): n / kMinErrorBatches, so that the problem

@@ -16,8 +16,9 @@
 // runs the item once it is published. Requests that arrive while the round
 // still has work to publish join it at once. The worker closes the round when
 // it has nothing left to publish (waves waiting in a round slow the waves that
-// run, so they leave at once, and a later request starts a fresh round), or
-// after a time slice when a request it cannot take waits (the other
+// run) and its waves start running out of work (while most are still busy,
+// requests that arrive join it at once instead of waiting for its last
+// chunks and a fresh round), or after a time slice when a request it cannot take waits (the other
 // precision, or a mesh finer than the round's LDS buffers); closing appends
 // one leave item per wave, so every item before them runs and every wave
 // leaves.
@@ -73,6 +74,11 @@ constexpr uint64_t kBulkAheadPerWave = 1;
 constexpr uint64_t kPriorityHistoriesPerWave = 256;
 // Time a round stays open while a request it cannot take is waiting.
 constexpr double kSliceSeconds = 0.010;
+// A round with nothing left to publish stays open while fewer than
+// 1 / kIdleCloseShare of its waves wait for an item, for at most kDrySeconds
+// (well within the waves' own wait limit).
+constexpr uint64_t kIdleCloseShare = 8;
+constexpr double kDrySeconds = 0.5;
 // Mesh capacity of a round's LDS buffers, at least (the served mix fits).
 constexpr int kServedMinBins = 1024;
 // A wave with nothing to run gives up on its ticket after about kWaitSeconds
@@ -130,6 +136,8 @@ struct RoundSlot {
     int serial = -1;
     Variant v;
     Clock::time_point opened;
+    bool dry = false;                    // nothing left to publish, since dry_since
+    Clock::time_point dry_since;
     int grid = 0, block = 0, waves = 0, max_bins = 0;   // max_bins: mesh capacity of its LDS buffers
     size_t lds = 0;
     // pinned host: feed, items, the table of entry records
@@ -490,6 +498,16 @@ bool round_has_work(cls_server *s, const RoundSlot &sl)
     return false;
 }
 
+// Whether the round's waves run out of work: at least 1 / kIdleCloseShare of
+// them hold a ticket beyond the published items (the waves report every 32nd
+// ticket they take).
+bool round_draining(const RoundSlot &sl)
+{
+    const uint64_t seen = __atomic_load_n(&sl.feed->seen, __ATOMIC_ACQUIRE);
+    const uint64_t waiting = seen > sl.n_items ? seen - sl.n_items : 0;
+    return waiting * kIdleCloseShare >= (uint64_t)sl.waves;
+}
+
 // Launch a round of variant v in a free slot, fed with what is waiting.
 cls_status open_round(cls_server *s, RoundSlot &sl, const Variant &v)
 {
@@ -529,6 +547,7 @@ cls_status open_round(cls_server *s, RoundSlot &sl, const Variant &v)
     std::memset(sl.feed, 0, sizeof(ServedFeed));
     sl.open = true;
     sl.opened = Clock::now();
+    sl.dry = false;
     // only requests whose mesh fits the round's buffers are fed to it
     feed_round(s, sl);
     hipStream_t stream = s->streams[sl.stream];
@@ -737,10 +756,11 @@ void worker_main(cls_server *s)
             retire_round(s, sl, q);
         }
         // feed the open round. It is closed once it has nothing left to
-        // publish (waves without work leave at once: waves waiting in a round
-        // slow the ones that run, and a request that arrives later starts a
-        // round of its own within tens of microseconds), and after a slice when
-        // a request it cannot take waits (other precision, finer mesh).
+        // publish and its waves start to run out of work (waves waiting in a
+        // round slow the ones that run, so they leave soon; while most are
+        // busy with their last chunks, a request that arrives joins the round
+        // at once), and after a slice when a request it cannot take waits
+        // (other precision, finer mesh).
         RoundSlot *open = nullptr;
         for (RoundSlot &sl : s->slots)
             if (sl.busy && sl.open) open = &sl;
@@ -748,8 +768,18 @@ void worker_main(cls_server *s)
             bool other = false;
             for (Request *r : s->active)
                 if (r->state == RQ_ACTIVE && r->has_unpublished() && !fits(*open, r)) other = true;
-            const double age = std::chrono::duration<double>(Clock::now() - open->opened).count();
-            if (!round_has_work(s, *open) || (other && age >= kSliceSeconds)) {
+            const Clock::time_point now = Clock::now();
+            const double age = std::chrono::duration<double>(now - open->opened).count();
+            const bool has_work = round_has_work(s, *open);
+            if (has_work) {
+                open->dry = false;
+            } else if (!open->dry) {
+                open->dry = true;
+                open->dry_since = now;
+            }
+            const bool dry_long =
+                open->dry && std::chrono::duration<double>(now - open->dry_since).count() >= kDrySeconds;
+            if ((!has_work && (round_draining(*open) || dry_long)) || (other && age >= kSliceSeconds)) {
                 close_round(*open);
                 open = nullptr;
             } else {
@@ -870,14 +900,15 @@ cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, 
     r->histories = histories;
     r->seed = seed;
     r->t_submit = Clock::now();
-    // chunks fixed by the request alone (never by the mix it meets), as in a
-    // batch of resident rounds: at least kMinErrorBatches when the history
-    // count allows, at most one wave's share of round_histories
+    // chunks fixed by the request alone (never by the mix it meets), for the
+    // waves of a round (one LDS buffer per wave, as open_round shapes it): at
+    // least kMinErrorBatches when the history count allows, up to one wave's
+    // share of round_histories, a whole number per wave for large requests
     int grid, block, stride;
     size_t lds;
     LaunchShape sh;
     cls_status st = shape_for(r->v, served_bins(p->nbins), s->di, &grid, &block, &lds, &stride, &sh,
-                              [](uint64_t, uint64_t) { return 1.0; });
+                              [](uint64_t, uint64_t) { return 0.0; });
     uint64_t *rec_dev = nullptr;
     if (st == CLS_OK) st = host_record_of(p, &rec_dev);
     if (st != CLS_OK) {
@@ -886,7 +917,7 @@ cls_status cls_server_submit(cls_server *s, cls_problem *p, uint64_t histories, 
     }
     const uint64_t waves_total = (uint64_t)std::max(1, grid - kReservedSlots) * (uint64_t)(block / 64);
     const uint64_t round_share = std::max<uint64_t>(1, s->cfg.round_histories / waves_total);
-    r->chunk = grouped_chunk_size(histories, waves_total, (uint64_t)sh.max_chunk, round_share);
+    r->chunk = served_chunk_size(histories, waves_total, (uint64_t)sh.max_chunk, round_share);
     r->n_chunks = (histories + r->chunk - 1) / r->chunk;
     r->priority = histories <= kPriorityHistoriesPerWave * waves_total;
     r->footprint = block_bytes(s, p->nbins);

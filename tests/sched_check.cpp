@@ -87,6 +87,36 @@ int main()
         ++cases;
     }
 
+    // a served request: a whole number of chunks per wave of the round once it
+    // has a wave's share for every wave
+    for (int t = 0; t < 100000; ++t) {
+        const uint64_t n = std::max<uint64_t>(1, log_uniform(1, 1e10));
+        const uint64_t w = log_uniform(1, 20000) + 1;
+        const uint64_t mc = max_chunks[t & 3];
+        const uint64_t share = log_uniform(1, 1e6) + 1;
+        const uint64_t c = served_chunk_size(n, w, mc, share);
+        CHECK(c >= 1 && c <= mc, "served n=%llu w=%llu mc=%llu share=%llu c=%llu", (unsigned long long)n,
+              (unsigned long long)w, (unsigned long long)mc, (unsigned long long)share, (unsigned long long)c);
+        const uint64_t chunks = chunks_of(n, c);
+        const uint64_t g = grouped_chunk_size(n, w, mc, share);
+        if (c != g) {
+            // the rule applied (a wave's share of at least 64 histories for every
+            // wave): the waves' last chunks end together, the chunk count filling
+            // the waves' turns (ceil(chunks / w) each) to within 1 / c (the
+            // rounding of the chunk), and the request keeps kMinErrorBatches chunks
+            const uint64_t per = std::min(share, mc);
+            CHECK(per >= 64 && n / w >= per, "served rule outside its range n=%llu w=%llu", (unsigned long long)n,
+                  (unsigned long long)w);
+            const uint64_t turns = (chunks + w - 1) / w;
+            CHECK(chunks * c >= turns * w * (c - 1), "served n=%llu w=%llu c=%llu chunks=%llu turns=%llu",
+                  (unsigned long long)n, (unsigned long long)w, (unsigned long long)c, (unsigned long long)chunks,
+                  (unsigned long long)turns);
+            CHECK(chunks >= std::min<uint64_t>(kMinErrorBatches, n), "served n=%llu c=%llu chunks=%llu",
+                  (unsigned long long)n, (unsigned long long)c, (unsigned long long)chunks);
+        }
+        ++cases;
+    }
+
     // round budget and water-filling
     for (int t = 0; t < 20000; ++t) {
         std::uniform_int_distribution<int> nreq(1, 60);
