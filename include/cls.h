@@ -81,8 +81,10 @@ enum {
                                        positions differ by rounding)                  */
 };
 
-/* Largest flux mesh. */
-#define CLS_MAX_BINS 2048
+/* Largest flux mesh. A wave's LDS tally buffer holds K + 1 doubles (plus ~350
+ * bytes of per-wave state): meshes beyond ~8140 bins need more than 64 KB per
+ * workgroup, which gfx950 allows (160 KB per CU), at 2 resident waves per CU. */
+#define CLS_MAX_BINS 8192
 
 typedef struct cls_problem cls_problem;
 
@@ -358,7 +360,7 @@ void cls_server_destroy(cls_server *s);
  * holds on each device it runs on until the process ends, and nothing is
  * copied to the host.
  *   p            a problem from cls_create_problem (only read; CLS_F_TRACE is
- *                rejected; nbins <= CLS_MAX_BINS).
+ *                rejected; nbins <= 2048, the meshes whose sums fit the 64 KB).
  *   hip_stream   hipStream_t the work is enqueued on (NULL = default stream);
  *                the call returns at once, the caller synchronizes.
  *   d_record     caller-owned device memory, 8-byte aligned, of at least
@@ -373,7 +375,7 @@ void cls_server_destroy(cls_server *s);
  * device (two streams, two threads) race and give wrong results; calls ordered
  * by the caller are independent.
  * Errors: CLS_ERR_INVALID_ARG (NULL arguments, histories == 0, trace problem,
- * nbins above CLS_MAX_BINS, record buffer too small or misaligned),
+ * nbins above 2048, record buffer too small or misaligned),
  * CLS_ERR_NO_DEVICE, CLS_ERR_DEVICE. */
 cls_status cls_run_static(const cls_problem *p, uint64_t histories, uint64_t seed, void *hip_stream,
                           void *d_record, size_t record_bytes);

@@ -44,7 +44,7 @@ CLS_F_FP32 = 1 << 2
 CLS_F_TRACE = 1 << 3
 CLS_F_TRACE_NO_BINS = 1 << 4
 
-CLS_MAX_BINS = 2048
+CLS_MAX_BINS = 8192
 
 EXPORTED = (
     "cls_create_problem", "cls_destroy_problem", "cls_set_stream", "cls_footprint",

@@ -329,8 +329,14 @@ cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *
     LaunchShape s = current_shape();
     int kp = max_bins + 1;
     kp += kp & 1;
-    const size_t limit = std::min(kLdsLimit, di.lds_per_block ? di.lds_per_block : kLdsLimit);
     auto wave_bytes = [&](int slots) { return ((size_t)slots * (size_t)kp + kWaveExtraDoubles) * sizeof(double); };
+    // workgroups take at most kLdsLimit, except for a mesh whose one buffer
+    // needs more than 32 KB (beyond ~4050 bins): then up to the device's limit
+    // per workgroup (gfx950: the CU's 160 KB), where two-wave workgroups fit
+    // (the occupancy query reports no room for one-wave workgroups of 48 KB
+    // or more of these kernels, measured on MI355X)
+    size_t limit = std::min(kLdsLimit, di.lds_per_block ? di.lds_per_block : kLdsLimit);
+    if (wave_bytes(1) > 32768 && di.lds_per_block > limit) limit = di.lds_per_block;
     if (wave_bytes(1) > limit) return fail(CLS_ERR_INVALID_ARG, "flux mesh too large for LDS");
     int best_waves = 0, best_bpc = 0, best_slots = 2;
     const int candidates[4] = {4, 8, 2, 1};
@@ -357,6 +363,7 @@ cls_status shape_for(const Variant &v, int max_bins, const DeviceInfo &di, int *
     const size_t per_wave = wave_bytes(best_waves ? best_slots : 1);
     if (best_waves == 0) best_slots = 1;
     if (best_waves == 0) {   // a fixed workgroup size that does not fit: shrink it
+        if (s.waves_per_block <= 0) return fail(CLS_ERR_INVALID_ARG, "no workgroup shape fits this flux mesh");
         best_waves = s.waves_per_block;
         while (best_waves > 1 && per_wave * (size_t)best_waves > limit) --best_waves;
         best_bpc = s.blocks_per_cu;

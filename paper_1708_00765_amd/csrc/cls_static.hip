@@ -29,10 +29,11 @@ using namespace cls::rt;
 
 namespace {
 
-// Largest flux mesh of an allocation-free run, and the scratch size it needs:
-// the problem record, the queue words, C_COUNT counters and 3 + 3K sums, each
-// section 256-byte aligned (40 KB for 2048 bins).
-constexpr int kStaticMaxBins = CLS_MAX_BINS;
+// Largest flux mesh of an allocation-free run (below CLS_MAX_BINS, to keep the
+// array modest), and the scratch size it needs: the problem record, the queue
+// words, C_COUNT counters and 3 + 3K sums, each section 256-byte aligned (50 KB
+// for 2048 bins).
+constexpr int kStaticMaxBins = 2048;
 constexpr size_t kScratchBytes = 64 * 1024;
 
 constexpr size_t kProbOff = 0;

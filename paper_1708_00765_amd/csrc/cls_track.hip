@@ -35,6 +35,8 @@
 //    over its histories of one chunk and reach the slot's LDS counters when
 //    the lane takes a history of another chunk or the slot is flushed;
 //    collisions and lateral reflections are derived when the record is made.
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "cls_internal.hpp"
@@ -1388,12 +1390,39 @@ static TrackFn pick(const Variant &v)
     }
 }
 
+// A workgroup above 64 KB of LDS (meshes beyond ~4050 bins take two-wave
+// workgroups of more than that; gfx950 allows the CU's 160 KB) needs the
+// kernel's attribute raised: once per kernel, to the CU's LDS, by the first
+// occupancy query (before any launch, outside any graph capture) or launch.
+// Smaller workgroups leave the attribute as it is.
+static hipError_t allow_lds(TrackFn f, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<TrackFn, bool> raised;
+    if (lds <= 65536) return hipSuccess;
+    std::lock_guard<std::mutex> lk(mu);
+    if (raised[f]) return hipSuccess;
+    int dev = 0, lds_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+    if (e == hipSuccess && (size_t)lds_cu < lds) e = hipErrorInvalidValue;
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize, lds_cu);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    raised[f] = true;
+    return hipSuccess;
+}
+
 hipError_t track_occupancy(const Variant &v, int block, size_t lds, int *blocks_per_cu)
 {
     const TrackFn f = pick(v);
     if (!f) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void *>(f),
-                                                        block, lds);
+    const hipError_t e = allow_lds(f, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void *>(f), block, lds);
 }
 
 hipError_t launch_track(const Variant &v, const TrackArgs &a, int grid, int block, size_t lds,
@@ -1401,6 +1430,8 @@ hipError_t launch_track(const Variant &v, const TrackArgs &a, int grid, int bloc
 {
     const TrackFn f = pick(v);
     if (!f || grid <= 0) return hipErrorInvalidValue;
+    const hipError_t e = allow_lds(f, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(f, dim3(grid), dim3(block), lds, s, a);
     return hipGetLastError();
 }

@@ -47,7 +47,7 @@ GOOD = dict(d=3, L=10.0, sigma_t=(0.5, 1.0), c=(0.2, 0.9), lam=(1.0, 0.3))
     dict(sigma_t=(0.0, 1.0)), dict(sigma_t=(1.0, -2.0)), dict(sigma_t=(math.nan, 1.0)),
     dict(c=(1.01, 0.5)), dict(c=(-0.1, 0.5)), dict(c=(math.nan, 0.5)),
     dict(lam=(0.0, 1.0)), dict(lam=(math.inf, 1.0)),
-    dict(source=2), dict(nbins=0), dict(nbins=2049), dict(flags=1 << 7),
+    dict(source=2), dict(nbins=0), dict(nbins=8193), dict(flags=1 << 7),
     dict(flags=1),                      # slab flag with d = 3
     dict(flags=1 << 4),                 # event-only trace hash without a trace
     dict(boundaries=0),                 # vacuum lateral faces

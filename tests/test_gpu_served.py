@@ -134,3 +134,23 @@ def test_served_requests_match_the_oracle(cls):
             n_bins += s.nbins
     print("FP32 served bins beyond 4 sigma", n_bins_bad, "of", n_bins, flush=True)
     assert n_bins_bad <= allowed_beyond_4(n_bins)
+
+
+def test_served_finest_mesh_follows_the_oracle(cls):
+    """A request at the largest mesh (CLS_MAX_BINS: its round's LDS tally buffers need
+    more than 64 KB per wave) beside a small rod request, FP64 on the oracle's streams:
+    counts equal and flux to 1e-9."""
+    mix = [(Spec(3, (0.5, 1.5), (0.5, 0.9), (1.0, 0.3), cls.CLS_MAX_BINS, 20000, 97001,
+                 name="served cube at the largest mesh"), False),
+           (Spec(1, (0.3, 1.2), (0.4, 0.8), (0.5, 2.0), 100, 5000, 97002, collision=True,
+                 name="served rod"), False)]
+    res, _, stats = _serve(cls, mix, record_path=0)
+    assert stats["completed"] == 2
+    for (s, _), (t, flux, _) in zip(mix, res):
+        g = tallies_dict(t)
+        o = run_oracle(s)
+        for k, ok in (("transmitted", o.transmitted), ("reflected", o.reflected), ("absorbed", o.absorbed),
+                      ("flights", o.flights), ("scatters", o.scatters), ("interface_crossings", o.interfaces),
+                      ("lateral_reflections", o.lateral)):
+            assert g[k] == ok, (s.name, k, g[k], ok)
+        np.testing.assert_allclose(flux, o.flux, rtol=1e-9, atol=1e-12, err_msg=s.name)

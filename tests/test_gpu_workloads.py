@@ -509,7 +509,8 @@ EDGE = [
     ("ragged tail 65", Spec(2, (0.5, 1.5), (0.5, 0.9), (1.0, 0.3), 50, 65, 13)),
     ("ragged 4099", Spec(1, (0.5, 1.5), (0.5, 0.9), (1.0, 0.3), 37, 4099, 14, collision=True)),
     ("one bin", Spec(3, (0.5, 1.5), (0.5, 0.9), (1.0, 0.3), 1, 5000, 15)),
-    ("max bins", Spec(3, (0.5, 1.5), (0.5, 0.9), (1.0, 0.3), 2048, 5000, 16)),
+    ("max bins", Spec(3, (0.5, 1.5), (0.5, 0.9), (1.0, 0.3), 8192, 5000, 16)),
+    ("max bins in 64 KB", Spec(2, (0.5, 1.5), (0.5, 0.9), (1.0, 0.3), 8100, 3000, 26)),
     ("pure absorber", Spec(3, (0.5, 1.5), (0.0, 0.0), (1.0, 0.3), 100, 5000, 17)),
     ("pure scatterer", Spec(2, (0.5, 1.5), (1.0, 1.0), (1.0, 0.3), 100, 5000, 18)),
     ("optically thin", Spec(3, (1e-4, 1e-4), (0.5, 0.5), (1e6, 1e6), 100, 5000, 19)),

@@ -112,6 +112,15 @@ def test_static_run_refuses_what_does_not_fit(env):
         with pytest.raises(cls.ClsError) as ei:
             cls.cls_run_static(p, 0, s.seed, None, buf.data_ptr(), cls.record_bytes(s.nbins))
         assert ei.value.status == cls.CLS_ERR_INVALID_ARG
+        # a valid mesh whose sums do not fit the static workspace (2048 bins at most)
+        fine = gpu_problem(Spec(3, (0.6, 1.4), (0.7, 0.95), (0.8, 0.4), 2049, 1000, 6104), fp32=True)
+        try:
+            big = torch.zeros(cls.record_bytes(2049) // 8, dtype=torch.int64, device="cuda")
+            with pytest.raises(cls.ClsError) as ei:
+                cls.cls_run_static(fine, 1000, 6104, None, big.data_ptr(), cls.record_bytes(2049))
+            assert ei.value.status == cls.CLS_ERR_INVALID_ARG
+        finally:
+            cls.cls_destroy_problem(fine)
     finally:
         cls.cls_destroy_problem(p)
         cls.cls_destroy_problem(t)
