@@ -289,9 +289,10 @@ cls_status cls_autotune(cls_problem *const *problems, const uint64_t *histories,
  * estimator and source of one precision, and takes its work from a queue in
  * pinned host memory that the worker feeds while it runs (small requests whole
  * as they arrive, large ones metered chunk by chunk), so a request that
- * arrives while the round still has work to publish joins it at once. The
- * round is closed (it drains; a later request starts a new one) once it has
- * nothing left to publish, and after a 10 ms slice when a request it cannot
+ * arrives while the round is open joins it at once. The round is closed (it
+ * drains; a later request starts a new one) once it has nothing left to
+ * publish and an eighth of its waves wait for work (at most 0.5 s after its
+ * last item), and after a 10 ms slice when a request it cannot
  * take waits (the other precision, or a mesh finer than its LDS buffers, which
  * hold at least 1024 bins). The wave that flushes a request's last chunk
  * signals the worker, which launches a finalize kernel for it while the round

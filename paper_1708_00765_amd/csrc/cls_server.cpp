@@ -13,12 +13,12 @@
 // arrive, large ones metered, about one chunk per wave ahead of the waves. A
 // wave takes the next item index with one fetch-add on a device counter (a
 // compare-and-swap claim collapses when thousands of waves contend for it) and
-// runs the item once it is published. Requests that arrive while the round
-// still has work to publish join it at once. The worker closes the round when
-// it has nothing left to publish (waves waiting in a round slow the waves that
-// run) and its waves start running out of work (while most are still busy,
-// requests that arrive join it at once instead of waiting for its last
-// chunks and a fresh round), or after a time slice when a request it cannot take waits (the other
+// runs the item once it is published. Requests that arrive while the round is
+// open join it at once. The worker closes the round when it has nothing left
+// to publish and its waves start running out of work (waves waiting in a
+// round slow the waves that run; while most are still busy, requests that
+// arrive join it at once instead of waiting for its last chunks and a fresh
+// round), or after a time slice when a request it cannot take waits (the other
 // precision, or a mesh finer than the round's LDS buffers); closing appends
 // one leave item per wave, so every item before them runs and every wave
 // leaves.
