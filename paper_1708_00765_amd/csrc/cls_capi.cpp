@@ -43,6 +43,9 @@ cls_status fail(cls_status s, const std::string &msg)
 cls_status hip_fail(hipError_t e, const char *what)
 {
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    // the failure is reported here; clear the thread's last HIP error so that
+    // the next launch check (hipGetLastError) does not report it again
+    (void)hipGetLastError();
     return fail(CLS_ERR_DEVICE, m);
 }
 
