@@ -168,6 +168,61 @@ def test_graph_replays_match_eager_runs(cls):
             cls.cls_destroy_problem(p)
 
 
+def test_ext2d_full_size_launch_shape_follows_the_oracle_fp64(cls):
+    """The twelve finest extruded meshes (up to 998 bins) with the full-size batch's
+    launch configuration (one LDS tally buffer per wave, the autotuner's 65536-history
+    chunk cap; the chunks themselves follow these smaller history counts), FP64 on the
+    oracle's streams at history counts the oracle finishes in seconds: counts equal and
+    flux to 1e-9 for every set."""
+    specs = workload("ext2d_batched")
+    sub = [Spec(s.d, s.sigma, s.c, s.lam, s.nbins, min(s.histories, 20_000), s.seed, name=s.name)
+           for s in sorted(specs, key=lambda s: -s.nbins)[:12]]
+    probs = [gpu_problem(s, fp32=False) for s in sub]
+    cls.cls_set_launch_config(max_chunk=65536, slots=1)
+    try:
+        cls.cls_run_batch(probs, [s.histories for s in sub], [s.seed for s in sub])
+        res = [cls.cls_read_tallies(p, s.nbins) for p, s in zip(probs, sub)]
+    finally:
+        cls.cls_set_launch_config(0, 0, 0, 0)
+        for p in probs:
+            cls.cls_destroy_problem(p)
+    for s, (t, flux, _) in zip(sub, res):
+        g = tallies_dict(t)
+        o = run_oracle(s)
+        for key, ok in (("transmitted", o.transmitted), ("reflected", o.reflected), ("absorbed", o.absorbed),
+                        ("flights", o.flights), ("scatters", o.scatters), ("interface_crossings", o.interfaces),
+                        ("lateral_reflections", o.lateral)):
+            assert g[key] == ok, (s.name, key, g[key], ok)
+        np.testing.assert_allclose(flux, o.flux, rtol=1e-9, atol=1e-12, err_msg=s.name)
+
+
+def test_graph_replays_follow_the_oracle_fp64(cls):
+    """FP64 graph replays on the oracle's streams (Algorithm A, Section 4): every replay,
+    with new history counts and seeds, gives the oracle's counts exactly and its flux
+    to 1e-9."""
+    specs = workload("cube3d_track", histories=20_000)[:3]
+    graph = [gpu_problem(s, fp32=False) for s in specs]
+    b = cls.cls_batch_create(graph)
+    try:
+        for k in range(2):
+            seeds = [s.seed + 7919 * (k + 1) for s in specs]
+            hist = [s.histories - 331 * k for s in specs]
+            cls.cls_batch_run(b, hist, seeds)
+            for s, p, n, sd in zip(specs, graph, hist, seeds):
+                t, flux, _ = cls.cls_read_tallies(p, s.nbins)
+                g = tallies_dict(t)
+                o = run_oracle(s, histories=n, seed=sd)
+                for key, ok in (("transmitted", o.transmitted), ("reflected", o.reflected),
+                                ("absorbed", o.absorbed), ("flights", o.flights), ("scatters", o.scatters),
+                                ("interface_crossings", o.interfaces), ("lateral_reflections", o.lateral)):
+                    assert g[key] == ok, (k, s.name, key, g[key], ok)
+                np.testing.assert_allclose(flux, o.flux, rtol=1e-9, atol=1e-12, err_msg=f"replay {k} {s.name}")
+    finally:
+        cls.cls_batch_destroy(b)
+        for p in graph:
+            cls.cls_destroy_problem(p)
+
+
 @pytest.mark.parametrize("fp32", [True, False])
 def test_results_do_not_depend_on_launch_shape_and_autotune(cls, fp32):
     """Counts exactly, score and flux sums to FP64 summation order, for launch
