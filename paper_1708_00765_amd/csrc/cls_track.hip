@@ -13,7 +13,9 @@
 // Design (MI355X, wave64):
 //  * one history per lane, all particle state in registers; a lane whose
 //    history ends takes the next history of its wave's work chunk at the top
-//    of the next step, so lanes stay busy until the chunk queue is empty;
+//    of the next step, so lanes stay busy until the chunk queue is empty; the
+//    lanes in flight are a wave mask, which a lane reads with no vector
+//    instruction (inverse ballot);
 //  * every step consumes exactly one Philox block per lane (source step or
 //    flight), so the random-number work never diverges;
 //  * the source and the scattering direction share one direction sampler;
@@ -28,6 +30,9 @@
 //    the chunks a wave takes of one problem join the batch it is filling up
 //    to the problem's batch size, so a launch flushes about one batch per wave
 //    and problem instead of one per chunk (served rounds flush every chunk);
+//  * a served round runs every kind of problem of one precision, each kind in
+//    a tracking loop of its own (compiled as a batch kernel's is), entered for
+//    the kind of the chunk the wave holds;
 //  * track-length flux goes to the LDS buffer in difference form (four LDS
 //    FP64 atomics per flight whatever the number of bins crossed); the flush
 //    prefix-scans it across the wave;
