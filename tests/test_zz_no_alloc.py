@@ -81,16 +81,23 @@ def test_static_runs_equal_cls_run(env, fp32, chunk_batches):
                 np.testing.assert_allclose(fsig, rfsig, rtol=1e-8, atol=1e-14)
             else:
                 # batch-means errors from two batchings of the same histories:
-                # each has a relative spread of about 1 / sqrt(2 (B - 1))
+                # in a bin whose error is small against its value (many batches
+                # score in it) each has a relative spread of about
+                # 1 / sqrt(2 (B - 1)); in sparsely hit bins the estimate is not
+                # Gaussian, so those bins are checked through the median only
                 b = min(rec["batches"], ref["batches"])
                 assert b >= min(256, ref["histories"] // 64)
+                assert np.array_equal(fsig > 0, rfsig > 0)
                 ok = rfsig > 0
                 ratio = fsig[ok] / rfsig[ok]
+                dense = ok & (rfsig < 0.01 * np.abs(rflux))
+                rd = fsig[dense] / rfsig[dense]
                 tol = 8.0 / np.sqrt(2.0 * (b - 1))
-                print("batches", rec["batches"], ref["batches"], "flux sigma ratio", ratio.min(), ratio.max(),
-                      "tolerance", tol, flush=True)
-                assert np.all(np.abs(ratio - 1.0) <= tol)
-                assert np.array_equal(fsig > 0, rfsig > 0)
+                print("batches", rec["batches"], ref["batches"], "flux sigma ratio", ratio.min(), np.median(ratio),
+                      ratio.max(), "dense bins", int(dense.sum()), rd.min(), rd.max(), "tolerance", tol, flush=True)
+                assert dense.sum() >= 1
+                assert np.all(np.abs(rd - 1.0) <= tol)
+                assert abs(np.median(ratio) - 1.0) <= 0.05
             assert rec["transmitted"] + rec["reflected"] + rec["absorbed"] == s.histories
     finally:
         cls.cls_set_launch_config(0, 0, 0, 0)
